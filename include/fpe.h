@@ -1,0 +1,240 @@
+/* fpe.h — fast polynomial evaluation through evaluation trees on MI355X (gfx950).
+ *
+ * C-ABI of libfpe.so.  The library compiles a polynomial p under a function
+ * scheme f into an evaluation tree (G. Moroz, "Fast polynomial evaluation and
+ * composition", Section 1: Definition of evaluation tree; Section 1.1:
+ * Definition of function scheme), lays the tree out as a flat, topologically
+ * ordered node array, and runs the coefficient walk of Section 2.1 on the GPU
+ * at very many points at once, in
+ *   - plain FP64,
+ *   - compensated FP32 (double-float arithmetic with error-free TwoProd and
+ *     TwoSum, a running error bound, and an FP64 re-evaluation of every point
+ *     whose bound exceeds the requested tolerance), or
+ *   - exact arithmetic modulo the Mersenne prime 2^61 - 1,
+ * and composes p(q(x)) over Z/(2^31 - 1) through the same tree.
+ *
+ * Conventions
+ *  - Every function returns an fpe_status (0 = OK, < 0 = error) and never
+ *    throws or aborts across the ABI; fpe_last_error() gives a message for the
+ *    last failing call on the calling thread.
+ *  - "device" pointers are HIP device memory (for example torch tensors on a
+ *    ROCm build, passed as data_ptr()).  The caller owns every point, output,
+ *    workspace and q buffer.  The library owns the host side of a tree; the
+ *    device image of a tree lives in a caller-owned device buffer handed to
+ *    fpe_tree_upload.
+ *  - "stream" is a hipStream_t (NULL = the default stream).  Calls that take
+ *    a stream are asynchronous on it and make no hidden synchronisation.
+ *  - Validation errors are reported synchronously.  A device error surfaces as
+ *    FPE_EDEVICE at the next call that checks the stream.
+ */
+#ifndef FPE_H
+#define FPE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  FPE_OK = 0,
+  FPE_EINVAL = -1,        /* invalid argument (shape, scheme, duplicate term, residue >= p, ...) */
+  FPE_ENOMEM = -2,        /* host allocation failed, or a caller buffer is too small */
+  FPE_EDEVICE = -3,       /* a HIP call failed */
+  FPE_EBUDGET = -4,       /* the server's HBM budget cannot hold the request */
+  FPE_EUNSUPPORTED = -5,  /* valid, but outside what the kernels support (see each call) */
+  FPE_EBUSY = -6          /* the server has no free slot right now (retry later) */
+} fpe_status;
+
+/* Message for the last failing call on this thread; valid until the next call. */
+const char* fpe_last_error(void);
+
+/* Library version, e.g. "fpe 1.0 gfx950". */
+const char* fpe_version(void);
+
+typedef enum {
+  FPE_F64 = 0,   /* plain FP64 walk, one fused multiply-add per node (Section 2.1) */
+  FPE_F32C = 1,  /* compensated FP32 (double-float) walk + FP64 fallback */
+  FPE_MODP = 2   /* exact walk in Z/pZ, p = 2^61 - 1 for evaluation, 2^31 - 1 for composition */
+} fpe_domain;
+
+/* Function schemes (Section 1.1 and 1.2).  The argument of f is the degree n
+ * of the sub-polynomial being split as p = a x^{f(n)} + b, and 0 < f(n) <= n. */
+typedef enum {
+  FPE_DIRECT = 0,          /* D(n) = n                                      */
+  FPE_HORNER = 1,          /* H(n) = 1                                      */
+  FPE_ESTRIN = 2,          /* E(n) = 2^floor(log2 n)                        */
+  FPE_BALANCED = 3,        /* B(n) = ceil(n / 2)  (Section 1.2, on the degree) */
+  FPE_BALANCED_FLOOR = 4,  /* max(1, floor(n / 2)): the literal formula, for comparison */
+  FPE_THRESHOLD = 5,       /* E(n) if n > threshold, else H(n) (Section 1.1, Remark) */
+  FPE_TABLE = 6            /* user scheme: f(n) = table[n], each entry validated in [1, n] */
+} fpe_scheme_kind;
+
+typedef struct {
+  int32_t kind;            /* fpe_scheme_kind */
+  int32_t threshold;       /* FPE_THRESHOLD only */
+  const int32_t* table;    /* FPE_TABLE only: host array, table[n] for 1 <= n < table_len */
+  int32_t table_len;
+} fpe_scheme;
+
+/* One node of the compiled tree, in the order <_t of Section 1: decreasing
+ * lexicographic order of the monomials, index 0 is the biggest, the root is
+ * last, and every child has a lower index than its parent.  Each non-root
+ * node's partial degree d(N) = exp(N) - exp(parent(N)) has exactly one
+ * nonzero variable (var, pdeg); the root's partial degree is its own monomial
+ * (var, pdeg), pdeg = 0 if p has a constant term.  Junction nodes (flag
+ * FPE_NODE_JUNCTION, coefficient 0) are added only for sparse multivariate
+ * input whose nested coefficient polynomial has no constant term. */
+typedef struct {
+  union { double f; uint64_t u; } coef;  /* FP64 value, or residue (row 0 for a batch) */
+  int32_t pdeg;         /* partial degree in variable var */
+  uint8_t var;          /* 0-based variable index, x1 outermost */
+  uint8_t slot;         /* accumulator slot of the walk (Section 1.3, safe reading) */
+  uint8_t lazy_height;  /* lh(N) exactly as defined in Section 1.3 */
+  uint8_t flags;        /* FPE_NODE_* */
+  int32_t parent;       /* index of the parent, -1 for the root */
+  int32_t sub_begin;    /* the subtree of node i is [sub_begin, i]; its children lie in it */
+} fpe_node;
+
+#define FPE_NODE_LEAF 1u
+#define FPE_NODE_FIRST_CHILD 2u   /* C_1 of its parent (the biggest child) */
+#define FPE_NODE_JUNCTION 4u
+#define FPE_NODE_ROOT 8u
+
+typedef struct fpe_tree fpe_tree;
+
+/* Compile p = sum_t coeffs[t] * prod_j x_j^exps[t*nvars + j] under scheme f.
+ *   nvars   1..8
+ *   nterms  >= 1 terms; exponents >= 0 and < 2^20; no monomial twice.
+ *           Terms with a zero coefficient are dropped (all zero: FPE_EINVAL).
+ *   coeffs  host array: double[nterms] for FPE_F64 / FPE_F32C (finite), or
+ *           uint64_t[batch * nterms] residues < modulus for FPE_MODP (row r
+ *           holds instance r; all rows share the exponents; the tree shape is
+ *           taken from the union of nonzero positions).
+ *   batch   1 for evaluation; the number of instances for fpe_compose.
+ *   modulus FPE_MODP only: 2^61 - 1 (evaluation) or 2^31 - 1 (composition).
+ * On success *out owns a new tree (free with fpe_tree_free). */
+fpe_status fpe_compile(int32_t nvars, int64_t nterms, const int32_t* exps, const void* coeffs,
+                       int64_t batch, int32_t domain, uint64_t modulus, const fpe_scheme* f,
+                       fpe_tree** out);
+
+void fpe_tree_free(fpe_tree* t);
+
+/* Read-only view of the node array (valid while the tree lives). */
+fpe_status fpe_tree_nodes(const fpe_tree* t, const fpe_node** nodes, int64_t* n, int32_t* max_slot);
+
+/* Walk statistics: stack depth of the walk, size of the per-point power table,
+ * length of the power chain, number of distinct partial degrees. */
+typedef struct {
+  int64_t n_nodes;
+  int64_t n_terms;         /* nonzero input terms (n_nodes minus junctions) */
+  int32_t nvars;
+  int32_t max_slot;        /* largest safe slot */
+  int32_t max_lazy_height; /* largest lh(N) by the definition of Section 1.3 */
+  int32_t walk_depth;      /* accumulators live at once in the GPU walk */
+  int32_t n_powers;        /* distinct (variable, partial degree) pairs */
+  int32_t n_table;         /* powers held per point in the table (incl. chain temporaries) */
+  int32_t n_chain;         /* steps of the power chain (Section 2.2, fast exponentiation) */
+  int32_t n_offtable;      /* walk steps whose power is computed on the fly */
+} fpe_tree_info;
+
+fpe_status fpe_tree_get_info(const fpe_tree* t, fpe_tree_info* info);
+
+/* Exponent vector of node i (nvars entries, the node's monomial). */
+fpe_status fpe_tree_node_exps(const fpe_tree* t, int64_t i, int32_t* exps_out);
+
+/* Device image: its size, and its upload into a caller-owned device buffer of
+ * at least that many bytes (256-byte aligned).  The tree records the buffer;
+ * the buffer must outlive every evaluation that uses it.  Asynchronous on
+ * stream: the host copy is staged so the call may return before the copy. */
+size_t fpe_tree_device_bytes(const fpe_tree* t);
+fpe_status fpe_tree_upload(fpe_tree* t, void* dev_buf, size_t bytes, void* stream);
+
+/* Serialise the host tree (node array, program, coefficients) into a byte
+ * buffer and back, for reloading resident trees; *bytes in/out. */
+fpe_status fpe_tree_serialize(const fpe_tree* t, void* buf, size_t* bytes);
+fpe_status fpe_tree_deserialize(const void* buf, size_t bytes, fpe_tree** out);
+
+typedef struct {
+  double tol;               /* FPE_F32C: relative tolerance; points whose running error
+                               bound exceeds tol*|y| are re-evaluated in FP64.  <= 0 means 1e-12. */
+  int32_t force;            /* FPE_F32C: 0 = by bound, 1 = re-evaluate every point, 2 = never */
+  int32_t points_per_lane;  /* 0 = library default */
+  float* cond_out;          /* optional device float[npts]: ptilde(|x|)/|y| (FPE_F32C) */
+  uint32_t* flags_out;      /* optional device uint32[ceil(npts/32)]: fallback bitmask (FPE_F32C) */
+  void* workspace;          /* FPE_F32C: device buffer of fpe_workspace_bytes() bytes */
+  size_t workspace_bytes;
+  int64_t* nfallback_out;   /* optional device int64: number of re-evaluated points (FPE_F32C) */
+  void* ev_walk_begin;      /* optional hipEvent_t recorded on the stream right before the walk kernel */
+  void* ev_walk_end;        /* optional hipEvent_t recorded right after it (before any fallback) */
+} fpe_eval_opts;
+
+/* Workspace needed by fpe_evaluate for npts points (0 unless FPE_F32C). */
+size_t fpe_workspace_bytes(const fpe_tree* t, int64_t npts);
+
+/* Evaluate the uploaded tree at npts points.
+ *   pts  host array of nvars device pointers, each to npts values (SoA):
+ *        double for FPE_F64 / FPE_F32C, uint64_t residues < p for FPE_MODP.
+ *   out  device array of npts doubles (FPE_F64, FPE_F32C) or uint64_t (FPE_MODP).
+ *   opts may be NULL for FPE_F64 / FPE_MODP.
+ * Errors: FPE_EINVAL (not uploaded, npts < 0, NULL pointers), FPE_ENOMEM
+ * (workspace too small), FPE_EUNSUPPORTED (walk deeper than the kernels hold),
+ * FPE_EDEVICE. */
+fpe_status fpe_evaluate(const fpe_tree* t, const void* const* pts, int64_t npts, void* out,
+                        const fpe_eval_opts* opts, void* stream);
+
+/* Composition over Z/(2^31 - 1): for every instance r of the batch compiled into t
+ * (univariate, FPE_MODP, modulus 2^31 - 1), out[r] = p_r(q_r(x)).
+ *   q    device uint32[batch * (dq + 1)], coefficient j of instance r at r*(dq+1)+j, < p
+ *   out  device uint32[batch * (deg_p * dq + 1)], coefficients by exponent
+ *   workspace  device buffer of fpe_compose_workspace_bytes() bytes */
+size_t fpe_compose_workspace_bytes(const fpe_tree* t, int32_t dq);
+fpe_status fpe_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out,
+                       void* workspace, size_t workspace_bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: a persistent request loop with continuous batching.
+ * Requests of uneven size are admitted while their bytes fit the HBM budget
+ * and a slot is free; admitted requests are packed into one fused launch
+ * (a work table of (tree, point range) blocks) replayed through a HIP graph;
+ * requests arriving while a batch runs join the next one.  The server keeps
+ * uploaded trees resident (by the caller's device image) and records the
+ * latency of every request from submit to completion.
+ * ---------------------------------------------------------------------- */
+typedef struct fpe_server fpe_server;
+
+typedef struct {
+  const fpe_tree* tree;     /* compiled for FPE_F64 or FPE_F32C and uploaded */
+  const double* pts[8];     /* nvars device pointers (SoA) */
+  int64_t npts;
+  double* out;              /* device double[npts] */
+  float* cond_out;          /* optional device float[npts] */
+  double tol;               /* FPE_F32C tolerance (<= 0: 1e-12) */
+  int32_t domain;           /* FPE_F64 or FPE_F32C */
+} fpe_request;
+
+typedef struct {
+  int64_t submitted, completed, rejected;
+  int64_t batches;
+  double p50_ms, p99_ms, mean_ms;   /* submit -> completion latency */
+  double term_evals;                /* sum of nonzero terms x points over completed requests */
+  double busy_s;                    /* wall time with work on the GPU */
+  double fallback_frac;             /* re-evaluated points / points (FPE_F32C requests) */
+  int64_t hbm_in_use;               /* workspace bytes held by admitted requests */
+} fpe_stats;
+
+/* hbm_budget: bytes of device workspace the server may hold at once (it
+ * allocates them once, here); max_inflight: requests admitted at once. */
+fpe_status fpe_server_create(size_t hbm_budget, int32_t max_inflight, void* stream, fpe_server** out);
+fpe_status fpe_server_submit(fpe_server* s, const fpe_request* r, uint64_t* ticket);  /* non-blocking */
+fpe_status fpe_server_poll(fpe_server* s, uint64_t ticket, int32_t* done);
+fpe_status fpe_server_wait(fpe_server* s, uint64_t ticket);
+fpe_status fpe_server_drain(fpe_server* s);
+fpe_status fpe_server_stats(fpe_server* s, fpe_stats* st);
+void fpe_server_destroy(fpe_server* s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FPE_H */

@@ -1,0 +1,344 @@
+"""fpe: fast polynomial evaluation through evaluation trees on MI355X (gfx950).
+
+Thin ctypes binding over libfpe.so (include/fpe.h).  Argument marshalling
+only: every step of compile, evaluate and compose runs in the native library
+(host C++ for the tree compiler, HIP kernels for everything per point).
+PyTorch provides device memory and streams.  Importing this package fails
+loudly when libfpe.so has not been built.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfpe.so")
+
+F64, F32C, MODP = 0, 1, 2
+DIRECT, HORNER, ESTRIN, BALANCED, BALANCED_FLOOR, THRESHOLD, TABLE = range(7)
+SCHEMES = {"direct": DIRECT, "horner": HORNER, "estrin": ESTRIN, "balanced": BALANCED,
+           "balanced_floor": BALANCED_FLOOR, "threshold": THRESHOLD, "table": TABLE}
+P61 = (1 << 61) - 1
+P31 = (1 << 31) - 1
+
+NODE_LEAF, NODE_FIRST_CHILD, NODE_JUNCTION, NODE_ROOT = 1, 2, 4, 8
+
+
+class FpeError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"fpe status {status}: {msg}")
+        self.status = status
+
+
+class _Scheme(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("threshold", ctypes.c_int32),
+                ("table", ctypes.POINTER(ctypes.c_int32)), ("table_len", ctypes.c_int32)]
+
+
+class Node(ctypes.Structure):
+    _fields_ = [("coef", ctypes.c_uint64), ("pdeg", ctypes.c_int32), ("var", ctypes.c_uint8),
+                ("slot", ctypes.c_uint8), ("lazy_height", ctypes.c_uint8), ("flags", ctypes.c_uint8),
+                ("parent", ctypes.c_int32), ("sub_begin", ctypes.c_int32)]
+
+
+class TreeInfo(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_terms", ctypes.c_int64), ("nvars", ctypes.c_int32),
+                ("max_slot", ctypes.c_int32), ("max_lazy_height", ctypes.c_int32),
+                ("walk_depth", ctypes.c_int32), ("n_powers", ctypes.c_int32),
+                ("n_table", ctypes.c_int32), ("n_chain", ctypes.c_int32),
+                ("n_offtable", ctypes.c_int32)]
+
+
+class EvalOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("force", ctypes.c_int32),
+                ("points_per_lane", ctypes.c_int32), ("cond_out", ctypes.c_void_p),
+                ("flags_out", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
+                ("workspace_bytes", ctypes.c_size_t), ("nfallback_out", ctypes.c_void_p),
+                ("ev_walk_begin", ctypes.c_void_p), ("ev_walk_end", ctypes.c_void_p)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("tree", ctypes.c_void_p), ("pts", ctypes.c_void_p * 8), ("npts", ctypes.c_int64),
+                ("out", ctypes.c_void_p), ("cond_out", ctypes.c_void_p), ("tol", ctypes.c_double),
+                ("domain", ctypes.c_int32)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("submitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("rejected", ctypes.c_int64), ("batches", ctypes.c_int64),
+                ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
+                ("term_evals", ctypes.c_double), ("busy_s", ctypes.c_double),
+                ("fallback_frac", ctypes.c_double), ("hbm_in_use", ctypes.c_int64)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
+                          "python paper_1307_5655_amd/build.py")
+    L = ctypes.CDLL(LIB_PATH)
+    P, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+    sig = {
+        "fpe_last_error": ([], ctypes.c_char_p),
+        "fpe_version": ([], ctypes.c_char_p),
+        "fpe_compile": ([i32, i64, P, P, i64, i32, u64, ctypes.POINTER(_Scheme), ctypes.POINTER(P)], i32),
+        "fpe_tree_free": ([P], None),
+        "fpe_tree_nodes": ([P, ctypes.POINTER(ctypes.POINTER(Node)), ctypes.POINTER(i64),
+                            ctypes.POINTER(i32)], i32),
+        "fpe_tree_get_info": ([P, ctypes.POINTER(TreeInfo)], i32),
+        "fpe_tree_node_exps": ([P, i64, P], i32),
+        "fpe_tree_device_bytes": ([P], sz),
+        "fpe_tree_upload": ([P, P, sz, P], i32),
+        "fpe_tree_serialize": ([P, P, ctypes.POINTER(sz)], i32),
+        "fpe_tree_deserialize": ([P, sz, ctypes.POINTER(P)], i32),
+        "fpe_workspace_bytes": ([P, i64], sz),
+        "fpe_evaluate": ([P, P, i64, P, ctypes.POINTER(EvalOpts), P], i32),
+        "fpe_compose_workspace_bytes": ([P, i32], sz),
+        "fpe_compose": ([P, P, i32, P, P, sz, P], i32),
+        "fpe_server_create": ([sz, i32, P, ctypes.POINTER(P)], i32),
+        "fpe_server_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(u64)], i32),
+        "fpe_server_poll": ([P, u64, ctypes.POINTER(i32)], i32),
+        "fpe_server_wait": ([P, u64], i32),
+        "fpe_server_drain": ([P], i32),
+        "fpe_server_stats": ([P, ctypes.POINTER(Stats)], i32),
+        "fpe_server_destroy": ([P], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    return L
+
+
+lib = _load()
+
+EXPORTED = ["fpe_last_error", "fpe_version", "fpe_compile", "fpe_tree_free", "fpe_tree_nodes",
+            "fpe_tree_get_info", "fpe_tree_node_exps", "fpe_tree_device_bytes", "fpe_tree_upload",
+            "fpe_tree_serialize", "fpe_tree_deserialize", "fpe_workspace_bytes", "fpe_evaluate",
+            "fpe_compose_workspace_bytes", "fpe_compose", "fpe_server_create", "fpe_server_submit",
+            "fpe_server_poll", "fpe_server_wait", "fpe_server_drain", "fpe_server_stats",
+            "fpe_server_destroy"]
+
+
+def _check(st: int):
+    if st != 0:
+        raise FpeError(st, (lib.fpe_last_error() or b"").decode())
+
+
+def _stream_ptr(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _scheme(scheme, threshold: int = 10, table=None):
+    if isinstance(scheme, str):
+        scheme = SCHEMES[scheme]
+    s = _Scheme(scheme, threshold, None, 0)
+    keep = None
+    if scheme == TABLE:
+        keep = np.ascontiguousarray(table, dtype=np.int32)
+        s.table = keep.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        s.table_len = len(keep)
+    return s, keep
+
+
+class Tree:
+    """A compiled evaluation tree (fpe_compile) and its device image."""
+
+    def __init__(self, exps, coeffs, scheme="balanced", domain=F64, modulus=0, threshold=10,
+                 table=None):
+        exps = np.ascontiguousarray(np.asarray(exps, dtype=np.int32))
+        if exps.ndim == 1:
+            exps = exps.reshape(-1, 1)
+        nterms, nvars = exps.shape
+        if domain == MODP:
+            c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.uint64))
+            batch = 1 if c.ndim == 1 else c.shape[0]
+            c = c.reshape(batch, nterms)
+        else:
+            c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.float64))
+            batch = 1
+        sch, keep = _scheme(scheme, threshold, table)
+        h = ctypes.c_void_p()
+        _check(lib.fpe_compile(nvars, nterms, exps.ctypes.data_as(ctypes.c_void_p),
+                               c.ctypes.data_as(ctypes.c_void_p), batch, domain, modulus,
+                               ctypes.byref(sch), ctypes.byref(h)))
+        self._h = h
+        self.nvars, self.domain, self.modulus, self.batch = nvars, domain, modulus, batch
+        self._dev = None
+        info = TreeInfo()
+        _check(lib.fpe_tree_get_info(self._h, ctypes.byref(info)))
+        self.info = info
+
+    @classmethod
+    def _from_handle(cls, h, domain, modulus, batch):
+        self = cls.__new__(cls)
+        self._h = h
+        info = TreeInfo()
+        _check(lib.fpe_tree_get_info(h, ctypes.byref(info)))
+        self.info = info
+        self.nvars, self.domain, self.modulus, self.batch = info.nvars, domain, modulus, batch
+        self._dev = None
+        return self
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            lib.fpe_tree_free(h)
+            self._h = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def nodes(self):
+        """The node array as a structured numpy array (copy)."""
+        p = ctypes.POINTER(Node)()
+        n = ctypes.c_int64()
+        ms = ctypes.c_int32()
+        _check(lib.fpe_tree_nodes(self._h, ctypes.byref(p), ctypes.byref(n), ctypes.byref(ms)))
+        dt = np.dtype([("coef", "<u8"), ("pdeg", "<i4"), ("var", "u1"), ("slot", "u1"),
+                       ("lazy_height", "u1"), ("flags", "u1"), ("parent", "<i4"), ("sub_begin", "<i4")])
+        buf = ctypes.string_at(p, n.value * ctypes.sizeof(Node))
+        return np.frombuffer(buf, dtype=dt).copy()
+
+    def node_exps(self):
+        n = self.info.n_nodes
+        out = np.empty((n, self.nvars), dtype=np.int32)
+        row = np.empty(self.nvars, dtype=np.int32)
+        for i in range(n):
+            _check(lib.fpe_tree_node_exps(self._h, i, row.ctypes.data_as(ctypes.c_void_p)))
+            out[i] = row
+        return out
+
+    def device_bytes(self) -> int:
+        return int(lib.fpe_tree_device_bytes(self._h))
+
+    def upload(self, device="cuda", stream=None):
+        import torch
+        nb = self.device_bytes()
+        buf = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        off = (-buf.data_ptr()) % 256
+        view = buf[off:off + nb]
+        _check(lib.fpe_tree_upload(self._h, ctypes.c_void_p(view.data_ptr()), nb, _stream_ptr(stream)))
+        self._dev = buf          # keeps the device image alive
+        return self
+
+    def serialize(self) -> bytes:
+        n = ctypes.c_size_t(0)
+        _check(lib.fpe_tree_serialize(self._h, None, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        _check(lib.fpe_tree_serialize(self._h, buf, ctypes.byref(n)))
+        return buf.raw[: n.value]
+
+    @classmethod
+    def deserialize(cls, data: bytes, domain=F64, modulus=0, batch=1):
+        h = ctypes.c_void_p()
+        _check(lib.fpe_tree_deserialize(data, len(data), ctypes.byref(h)))
+        return cls._from_handle(h, domain, modulus, batch)
+
+
+def workspace_bytes(tree: Tree, npts: int) -> int:
+    return int(lib.fpe_workspace_bytes(tree.handle, npts))
+
+
+def evaluate(tree: Tree, pts, out=None, tol: float = 1e-12, force: int = 0, cond_out=None,
+             flags_out=None, workspace=None, nfallback_out=None, stream=None, events=None):
+    """Evaluate ``tree`` at device points ``pts`` (list of 1-D tensors, one per
+    variable; float64, or uint64 residues stored as int64 for FPE_MODP)."""
+    import torch
+    if tree._dev is None:
+        raise FpeError(-1, "tree is not uploaded")
+    pts = list(pts) if isinstance(pts, (list, tuple)) else [pts]
+    npts = pts[0].numel()
+    if out is None:
+        dt = torch.int64 if tree.domain == MODP else torch.float64
+        out = torch.empty(npts, dtype=dt, device=pts[0].device)
+    arr = (ctypes.c_void_p * 8)(*[p.data_ptr() for p in pts])
+    opts = EvalOpts(tol, force, 0, cond_out.data_ptr() if cond_out is not None else None,
+                    flags_out.data_ptr() if flags_out is not None else None, None, 0,
+                    nfallback_out.data_ptr() if nfallback_out is not None else None)
+    if events is not None:
+        # raw hipEvent_t handles (ctypes.c_void_p or int)
+        opts.ev_walk_begin = getattr(events[0], "value", events[0])
+        opts.ev_walk_end = getattr(events[1], "value", events[1])
+    if tree.domain == F32C:
+        need = workspace_bytes(tree, npts)
+        if workspace is None:
+            workspace = torch.empty(need + 256, dtype=torch.uint8, device=pts[0].device)
+        off = (-workspace.data_ptr()) % 256
+        opts.workspace = workspace.data_ptr() + off
+        opts.workspace_bytes = workspace.numel() - off
+    _check(lib.fpe_evaluate(tree.handle, arr, npts, ctypes.c_void_p(out.data_ptr()),
+                            ctypes.byref(opts), _stream_ptr(stream)))
+    return out
+
+
+def compose(tree: Tree, q, out=None, workspace=None, stream=None):
+    """p_r(q_r(x)) mod 2^31-1 for every instance r compiled into ``tree``;
+    ``q`` is a device int32/uint32 tensor [batch, dq + 1]."""
+    import torch
+    if tree._dev is None:
+        raise FpeError(-1, "tree is not uploaded")
+    batch, dq1 = q.shape
+    dq = dq1 - 1
+    dp = int(tree.node_exps().max())
+    if out is None:
+        out = torch.empty((batch, dp * dq + 1), dtype=torch.int32, device=q.device)
+    need = int(lib.fpe_compose_workspace_bytes(tree.handle, dq))
+    if workspace is None:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=q.device)
+    off = (-workspace.data_ptr()) % 256
+    _check(lib.fpe_compose(tree.handle, ctypes.c_void_p(q.data_ptr()), dq,
+                           ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(workspace.data_ptr() + off),
+                           workspace.numel() - off, _stream_ptr(stream)))
+    return out
+
+
+class Server:
+    """Continuous-batching request loop (fpe_server_*)."""
+
+    def __init__(self, hbm_budget: int, max_inflight: int = 64, stream=None):
+        h = ctypes.c_void_p()
+        _check(lib.fpe_server_create(hbm_budget, max_inflight, _stream_ptr(stream), ctypes.byref(h)))
+        self._h = h
+
+    def submit(self, tree: Tree, pts, out, domain=F32C, tol=1e-12, cond_out=None) -> int:
+        r = Request()
+        r.tree = tree.handle
+        for j, p in enumerate(pts):
+            r.pts[j] = p.data_ptr()
+        r.npts = pts[0].numel()
+        r.out = out.data_ptr()
+        r.cond_out = cond_out.data_ptr() if cond_out is not None else None
+        r.tol = tol
+        r.domain = domain
+        t = ctypes.c_uint64()
+        _check(lib.fpe_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def poll(self, ticket: int) -> bool:
+        d = ctypes.c_int32()
+        _check(lib.fpe_server_poll(self._h, ticket, ctypes.byref(d)))
+        return bool(d.value)
+
+    def wait(self, ticket: int):
+        _check(lib.fpe_server_wait(self._h, ticket))
+
+    def drain(self):
+        _check(lib.fpe_server_drain(self._h))
+
+    def stats(self) -> Stats:
+        s = Stats()
+        _check(lib.fpe_server_stats(self._h, ctypes.byref(s)))
+        return s
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.fpe_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()

@@ -1,0 +1,278 @@
+// C-ABI entry points of libfpe.so (declared in include/fpe.h).
+#include <hip/hip_runtime.h>
+
+#include <cstring>
+#include <new>
+
+#include "fpe_internal.h"
+
+namespace fpe {
+fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, const void* coeffs,
+                        int64_t batch, int32_t domain, uint64_t modulus, const fpe_scheme* fs,
+                        fpe_tree** out);
+const char* last_error();
+
+namespace {
+inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+void layout(fpe_tree* t) {
+  size_t off = 0;
+  t->off_ops64 = off;
+  off = align256(off + t->ops64.size() * sizeof(OpF64));
+  t->off_ops32 = off;
+  off = align256(off + t->ops32.size() * sizeof(OpF32));
+  t->off_chain = off;
+  off = align256(off + std::max<size_t>(t->chain.size(), 1) * sizeof(ChainStep));
+  t->off_coef = off;
+  if (t->domain == FPE_MODP && t->modulus == kP31) off = align256(off + t->coef_rows.size() * sizeof(uint32_t));
+  t->dev_bytes = std::max<size_t>(off, 256);
+}
+}  // namespace
+
+DevTree dev_view(const fpe_tree* t) {
+  DevTree d{};
+  const char* b = (const char*)t->dev;
+  d.ops64 = (const OpF64*)(b + t->off_ops64);
+  d.ops32 = (const OpF32*)(b + t->off_ops32);
+  d.chain = (const ChainStep*)(b + t->off_chain);
+  d.coef_rows = (const uint32_t*)(b + t->off_coef);
+  d.n_ops = (int32_t)t->ops64.size();
+  d.n_chain = (int32_t)t->chain.size();
+  d.n_table = t->n_table;
+  d.nvars = t->nvars;
+  d.depth = t->depth;
+  d.n_nodes = (int32_t)t->nodes.size();
+  d.batch = t->batch;
+  return d;
+}
+
+}  // namespace fpe
+
+using namespace fpe;
+
+extern "C" {
+
+const char* fpe_last_error(void) { return fpe::last_error(); }
+
+const char* fpe_version(void) { return "fpe 1.0 gfx950"; }
+
+fpe_status fpe_compile(int32_t nvars, int64_t nterms, const int32_t* exps, const void* coeffs,
+                       int64_t batch, int32_t domain, uint64_t modulus, const fpe_scheme* f,
+                       fpe_tree** out) {
+  try {
+    fpe_status s = compile_tree(nvars, nterms, exps, coeffs, batch, domain, modulus, f, out);
+    if (s == FPE_OK) layout(*out);
+    return s;
+  } catch (const std::bad_alloc&) {
+    return fail(FPE_ENOMEM, "host allocation failed");
+  } catch (...) {
+    return fail(FPE_EINVAL, "unexpected error in compile");
+  }
+}
+
+void fpe_tree_free(fpe_tree* t) { delete t; }
+
+fpe_status fpe_tree_nodes(const fpe_tree* t, const fpe_node** nodes, int64_t* n, int32_t* max_slot) {
+  if (!t) return fail(FPE_EINVAL, "tree is NULL");
+  if (nodes) *nodes = t->nodes.data();
+  if (n) *n = (int64_t)t->nodes.size();
+  if (max_slot) *max_slot = t->max_slot;
+  return FPE_OK;
+}
+
+fpe_status fpe_tree_get_info(const fpe_tree* t, fpe_tree_info* info) {
+  if (!t || !info) return fail(FPE_EINVAL, "NULL argument");
+  std::memset(info, 0, sizeof *info);
+  info->n_nodes = (int64_t)t->nodes.size();
+  info->n_terms = t->n_terms;
+  info->nvars = t->nvars;
+  info->max_slot = t->max_slot;
+  info->max_lazy_height = t->max_lh;
+  info->walk_depth = t->depth;
+  info->n_powers = t->n_powers;
+  info->n_table = t->n_table;
+  info->n_chain = (int32_t)t->chain.size();
+  info->n_offtable = t->n_offtable;
+  return FPE_OK;
+}
+
+fpe_status fpe_tree_node_exps(const fpe_tree* t, int64_t i, int32_t* exps_out) {
+  if (!t || !exps_out) return fail(FPE_EINVAL, "NULL argument");
+  if (i < 0 || i >= (int64_t)t->nodes.size()) return fail(FPE_EINVAL, "node index out of range");
+  std::memcpy(exps_out, &t->exps[i * t->nvars], sizeof(int32_t) * t->nvars);
+  return FPE_OK;
+}
+
+size_t fpe_tree_device_bytes(const fpe_tree* t) { return t ? t->dev_bytes : 0; }
+
+fpe_status fpe_tree_upload(fpe_tree* t, void* dev_buf, size_t bytes, void* stream) {
+  if (!t || !dev_buf) return fail(FPE_EINVAL, "NULL argument");
+  if (bytes < t->dev_bytes) return fail(FPE_ENOMEM, "device buffer smaller than fpe_tree_device_bytes()");
+  if (((uintptr_t)dev_buf) & 255) return fail(FPE_EINVAL, "device buffer must be 256-byte aligned");
+  hipStream_t st = (hipStream_t)stream;
+  char* b = (char*)dev_buf;
+  hipError_t e = hipSuccess;
+  if (!t->ops64.empty())
+    e = hipMemcpyAsync(b + t->off_ops64, t->ops64.data(), t->ops64.size() * sizeof(OpF64),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !t->ops32.empty())
+    e = hipMemcpyAsync(b + t->off_ops32, t->ops32.data(), t->ops32.size() * sizeof(OpF32),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !t->chain.empty())
+    e = hipMemcpyAsync(b + t->off_chain, t->chain.data(), t->chain.size() * sizeof(ChainStep),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && t->domain == FPE_MODP && t->modulus == kP31) {
+    std::vector<uint32_t>* rows = new std::vector<uint32_t>(t->coef_rows.begin(), t->coef_rows.end());
+    e = hipMemcpy(b + t->off_coef, rows->data(), rows->size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    delete rows;
+  }
+  if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
+  t->dev = dev_buf;
+  return FPE_OK;
+}
+
+size_t fpe_workspace_bytes(const fpe_tree* t, int64_t npts) { return eval_workspace_bytes(t, npts); }
+
+fpe_status fpe_evaluate(const fpe_tree* t, const void* const* pts, int64_t npts, void* out,
+                        const fpe_eval_opts* opts, void* stream) {
+  if (!t) return fail(FPE_EINVAL, "tree is NULL");
+  if (!t->dev) return fail(FPE_EINVAL, "tree is not uploaded");
+  if (npts < 0) return fail(FPE_EINVAL, "npts < 0");
+  if (t->batch != 1) return fail(FPE_EINVAL, "a batch tree is for fpe_compose");
+  if (npts == 0) return FPE_OK;
+  if (!pts || !out) return fail(FPE_EINVAL, "NULL points or output");
+  for (int j = 0; j < t->nvars; ++j)
+    if (!pts[j]) return fail(FPE_EINVAL, "NULL point array");
+  return launch_eval(t, pts, npts, out, opts, stream);
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// serialisation of the host tree: a flat little-endian byte image
+// ---------------------------------------------------------------------------
+namespace {
+constexpr uint64_t kMagic = 0x3130455246505845ull;  // "EXPFREE01"-like tag
+struct Writer {
+  std::vector<char> b;
+  template <class T> void pod(const T& v) {
+    const char* p = (const char*)&v;
+    b.insert(b.end(), p, p + sizeof(T));
+  }
+  template <class T> void vec(const std::vector<T>& v) {
+    pod<uint64_t>(v.size());
+    const char* p = (const char*)v.data();
+    b.insert(b.end(), p, p + v.size() * sizeof(T));
+  }
+};
+struct Reader {
+  const char* p;
+  size_t n, o = 0;
+  bool ok = true;
+  template <class T> void pod(T& v) {
+    if (o + sizeof(T) > n) { ok = false; return; }
+    std::memcpy(&v, p + o, sizeof(T));
+    o += sizeof(T);
+  }
+  template <class T> void vec(std::vector<T>& v) {
+    uint64_t k = 0;
+    pod(k);
+    if (!ok || k > (n - o) / std::max<size_t>(sizeof(T), 1)) { ok = false; return; }
+    v.resize(k);
+    std::memcpy(v.data(), p + o, k * sizeof(T));
+    o += k * sizeof(T);
+  }
+};
+void write_tree(const fpe_tree* t, Writer& w) {
+  w.pod(kMagic);
+  w.pod(t->nvars); w.pod(t->domain); w.pod(t->modulus); w.pod(t->batch); w.pod(t->n_terms);
+  w.pod(t->n_table); w.pod(t->n_powers); w.pod(t->depth); w.pod(t->max_slot); w.pod(t->max_lh);
+  w.pod(t->n_offtable);
+  w.vec(t->nodes); w.vec(t->exps); w.vec(t->coef_rows); w.vec(t->ops64); w.vec(t->ops32);
+  w.vec(t->chain); w.vec(t->table_var); w.vec(t->table_deg);
+}
+}  // namespace
+
+extern "C" {
+
+fpe_status fpe_tree_serialize(const fpe_tree* t, void* buf, size_t* bytes) {
+  if (!t || !bytes) return fail(FPE_EINVAL, "NULL argument");
+  Writer w;
+  write_tree(t, w);
+  if (!buf) {
+    *bytes = w.b.size();
+    return FPE_OK;
+  }
+  if (*bytes < w.b.size()) {
+    *bytes = w.b.size();
+    return fail(FPE_ENOMEM, "buffer too small");
+  }
+  std::memcpy(buf, w.b.data(), w.b.size());
+  *bytes = w.b.size();
+  return FPE_OK;
+}
+
+fpe_status fpe_tree_deserialize(const void* buf, size_t bytes, fpe_tree** out) {
+  if (!buf || !out) return fail(FPE_EINVAL, "NULL argument");
+  Reader r{(const char*)buf, bytes};
+  uint64_t magic = 0;
+  r.pod(magic);
+  if (!r.ok || magic != kMagic) return fail(FPE_EINVAL, "not a serialised tree");
+  auto* t = new fpe_tree();
+  r.pod(t->nvars); r.pod(t->domain); r.pod(t->modulus); r.pod(t->batch); r.pod(t->n_terms);
+  r.pod(t->n_table); r.pod(t->n_powers); r.pod(t->depth); r.pod(t->max_slot); r.pod(t->max_lh);
+  r.pod(t->n_offtable);
+  r.vec(t->nodes); r.vec(t->exps); r.vec(t->coef_rows); r.vec(t->ops64); r.vec(t->ops32);
+  r.vec(t->chain); r.vec(t->table_var); r.vec(t->table_deg);
+  if (!r.ok || r.o != bytes || t->nvars < 1 || t->nvars > 8 ||
+      t->exps.size() != t->nodes.size() * (size_t)t->nvars || t->ops64.size() != t->nodes.size() ||
+      t->n_table < 0 || t->n_table > kMaxTable) {
+    delete t;
+    return fail(FPE_EINVAL, "corrupt serialised tree");
+  }
+  for (const auto& c : t->chain)
+    if (c.dst >= t->n_table || (c.kind == kChainMul && (c.s1 >= t->n_table || c.s2 >= t->n_table)) ||
+        (c.kind == kChainLoad && c.s1 >= t->nvars)) {
+      delete t;
+      return fail(FPE_EINVAL, "corrupt serialised tree (power chain)");
+    }
+  // the program is a balanced stack walk that ends with exactly one END
+  int32_t depth = 0, maxd = 0;
+  for (size_t k = 0; k < t->ops64.size(); ++k) {
+    uint32_t kind = op_kind(t->ops64[k].info);
+    if ((kind == kEnd) != (k + 1 == t->ops64.size())) depth = -1000;
+    if (kind == kLeafOpen) maxd = std::max(maxd, ++depth);
+    if (kind == kNodeAdd) --depth;
+    if ((kind == kLeafAdd || kind == kNodeOpen) && depth < 1) depth = -1000;
+    if (depth < 0) break;
+  }
+  if (depth < 0 || maxd > kMaxDepth || std::max(maxd, 1) != t->depth) {
+    delete t;
+    return fail(FPE_EINVAL, "corrupt serialised tree (walk)");
+  }
+  for (const auto& o : t->ops64) {
+    uint32_t p = op_pidx(o.info);
+    if (op_kind(o.info) > kEnd || (p != kOffTable && p >= (uint32_t)t->n_table) ||
+        op_var(o.info) >= (uint32_t)t->nvars) {
+      delete t;
+      return fail(FPE_EINVAL, "corrupt serialised tree (program)");
+    }
+  }
+  layout(t);
+  *out = t;
+  return FPE_OK;
+}
+
+size_t fpe_compose_workspace_bytes(const fpe_tree* t, int32_t dq) { return compose_workspace_bytes(t, dq); }
+
+fpe_status fpe_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* workspace,
+                       size_t workspace_bytes, void* stream) {
+  if (!t || !q || !out) return fail(FPE_EINVAL, "NULL argument");
+  if (!t->dev) return fail(FPE_EINVAL, "tree is not uploaded");
+  if (t->domain != FPE_MODP || t->modulus != kP31 || t->nvars != 1)
+    return fail(FPE_EINVAL, "composition needs a univariate tree compiled mod 2^31-1");
+  if (dq < 1) return fail(FPE_EINVAL, "deg q must be >= 1");
+  return launch_compose(t, q, dq, out, workspace, workspace_bytes, stream);
+}
+
+}  // extern "C"

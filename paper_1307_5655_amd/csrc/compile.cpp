@@ -1,0 +1,515 @@
+// Host compiler: polynomial + function scheme -> evaluation tree -> walk
+// program.  Everything here runs once per polynomial ("preprocessing" before
+// "subsequent fast evaluation", abstract and Section 1), on the CPU.
+//
+//  * terms are sorted in decreasing lexicographic order (the order <_t of
+//    Section 1: index 0 is the biggest monomial, the root is last);
+//  * the tree T_p^f is built by the split p = a x^{f(n)} + b of Section 1.1,
+//    with T_a grafted as a child of the root of T_b, applied to each variable
+//    in turn (Remark in Section 1.1), x1 outermost;
+//  * partial degrees are d(N) = exp(N) - exp(parent(N));
+//  * lazy heights follow Section 1.3; the walk itself uses the stack depth;
+//  * the distinct powers x_j^d are planned as a chain of multiplications
+//    (fast exponentiation, Section 2.2, Table 1).
+//
+// Readings where the paper is silent: f takes the degree n of the current
+// sub-polynomial measured from its exponent origin; if b = 0 the split adds
+// no node (the origin of a moves by f(n)); the balanced scheme is
+// B(n) = ceil(n/2) on the degree; a nested block whose coefficient polynomial
+// has no constant term gets a junction node with coefficient 0.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <unordered_map>
+
+#include "fpe_internal.h"
+
+namespace fpe {
+
+namespace {
+
+thread_local std::string g_err;
+
+struct Scheme {
+  int32_t kind;
+  int32_t threshold;
+  std::vector<int32_t> table;
+  // f(n) for n >= 1; returns <= 0 or > n for an illegal scheme
+  int64_t operator()(int64_t n) const {
+    switch (kind) {
+      case FPE_DIRECT: return n;
+      case FPE_HORNER: return 1;
+      case FPE_ESTRIN: {
+        int64_t e = 1;
+        while (e * 2 <= n) e *= 2;
+        return e;
+      }
+      case FPE_BALANCED: return (n + 1) / 2;
+      case FPE_BALANCED_FLOOR: return std::max<int64_t>(1, n / 2);
+      case FPE_THRESHOLD: {
+        if (n <= threshold) return 1;
+        int64_t e = 1;
+        while (e * 2 <= n) e *= 2;
+        return e;
+      }
+      case FPE_TABLE: return n < (int64_t)table.size() ? table[n] : -1;
+    }
+    return -1;
+  }
+};
+
+// Split a double into two floats whose sum rounds it to 48 bits.
+inline void split_f32(double v, float& h, float& l) {
+  h = (float)v;
+  l = (float)(v - (double)h);
+}
+
+inline float abs_up(double v) {
+  float f = (float)std::fabs(v);
+  return f == 0.f ? 0.f : std::nextafter(f, INFINITY);
+}
+
+}  // namespace
+
+void set_error(const std::string& msg) { g_err = msg; }
+fpe_status fail(fpe_status st, const std::string& msg) {
+  g_err = msg;
+  return st;
+}
+const char* last_error() { return g_err.c_str(); }
+
+namespace {
+
+struct Builder {
+  int32_t nv;
+  const std::vector<int32_t>& E;  // sorted terms x nv
+  const Scheme& f;
+  int64_t T;
+  std::vector<int64_t> parent;    // per node id (terms 0..T-1, then junctions)
+  std::vector<std::vector<int32_t>> jexps;
+  std::unordered_map<int64_t, int64_t> jmemo;  // (k * T + lo) -> node id
+  std::string err;
+
+  int32_t e(int64_t t, int k) const { return E[t * nv + k]; }
+
+  // first t in [lo, hi) with e(t, k) < v  (e(., k) is non-increasing on the range)
+  int64_t first_below(int64_t lo, int64_t hi, int k, int64_t v) const {
+    while (lo < hi) {
+      int64_t m = lo + (hi - lo) / 2;
+      if (e(m, k) < v) hi = m; else lo = m + 1;
+    }
+    return lo;
+  }
+  int64_t lowest_block(int64_t lo, int64_t hi, int k) const {
+    int32_t last = e(hi - 1, k);
+    // first t with e(t,k) <= last, i.e. first with e < last + 1
+    return first_below(lo, hi, k, (int64_t)last + 1);
+  }
+  int64_t junction(int k, int64_t lo) {
+    int64_t key = (int64_t)k * T + lo;
+    auto it = jmemo.find(key);
+    if (it != jmemo.end()) return it->second;
+    std::vector<int32_t> ex(nv, 0);
+    for (int j = 0; j <= k; ++j) ex[j] = e(lo, j);
+    int64_t id = T + (int64_t)jexps.size();
+    jexps.push_back(ex);
+    parent.push_back(-1);
+    jmemo[key] = id;
+    return id;
+  }
+  // node standing for the block [lo, hi) (one value of x_k) at level k
+  int64_t block_node(int k, int64_t lo, int64_t hi) {
+    for (;;) {
+      if (k == nv - 1) return lo;
+      if (e(hi - 1, k + 1) > 0) return junction(k, lo);
+      lo = lowest_block(lo, hi, k + 1);
+      ++k;
+    }
+  }
+
+  bool build() {
+    parent.assign(T, -1);
+    struct Task { int k; int64_t lo, hi, origin; };
+    std::vector<Task> st;
+    st.push_back({0, 0, T, 0});
+    while (!st.empty()) {
+      Task tk = st.back();
+      st.pop_back();
+      int k = tk.k;
+      if (e(tk.lo, k) == e(tk.hi - 1, k)) {   // one term in x_k: one node
+        if (k < nv - 1) {
+          if (e(tk.hi - 1, k + 1) > 0) {
+            int64_t J = junction(k, tk.lo);
+            int64_t inner = block_node(k + 1, lowest_block(tk.lo, tk.hi, k + 1), tk.hi);
+            parent[inner] = J;
+          }
+          st.push_back({k + 1, tk.lo, tk.hi, 0});
+        }
+        continue;
+      }
+      int64_t n = (int64_t)e(tk.lo, k) - tk.origin;
+      int64_t s = f(n);
+      if (s <= 0 || s > n) {
+        err = "scheme returned f(" + std::to_string(n) + ") = " + std::to_string(s) +
+              ", outside [1, n]";
+        return false;
+      }
+      int64_t mid = first_below(tk.lo, tk.hi, k, tk.origin + s);
+      if (mid == tk.hi) {                      // b = 0: p = a x^{f(n)}
+        st.push_back({k, tk.lo, tk.hi, tk.origin + s});
+        continue;
+      }
+      int64_t ra = block_node(k, lowest_block(tk.lo, mid, k), mid);
+      int64_t rb = block_node(k, lowest_block(mid, tk.hi, k), tk.hi);
+      parent[ra] = rb;                          // T_a under the root of T_b
+      st.push_back({k, tk.lo, mid, tk.origin + s});
+      st.push_back({k, mid, tk.hi, tk.origin});
+    }
+    return true;
+  }
+};
+
+// Plan the power table and chain (fast exponentiation): every used
+// (var, degree) gets a table entry; missing intermediate degrees are added by
+// halving, so x^d = x^{floor(d/2)} * x^{ceil(d/2)}.
+struct PowerPlan {
+  std::vector<std::pair<int32_t, int32_t>> entries;  // (var, deg)
+  std::vector<ChainStep> chain;
+  std::map<std::pair<int32_t, int32_t>, int32_t> index;
+  bool ok = true;
+
+  int32_t ensure(int32_t var, int32_t d, int32_t cap) {
+    auto key = std::make_pair(var, d);
+    auto it = index.find(key);
+    if (it != index.end()) return it->second;
+    int32_t a = -1, b = -1;
+    if (d > 1) {
+      int32_t h = d / 2;
+      a = ensure(var, h, cap);
+      b = ensure(var, d - h, cap);
+      if (a < 0 || b < 0) return -1;
+    }
+    if ((int32_t)entries.size() >= cap) {
+      ok = false;
+      return -1;
+    }
+    int32_t id = (int32_t)entries.size();
+    entries.push_back(key);
+    index[key] = id;
+    if (d == 1) chain.push_back({(uint8_t)kChainLoad, (uint8_t)id, (uint8_t)var, 0});
+    else chain.push_back({(uint8_t)kChainMul, (uint8_t)id, (uint8_t)a, (uint8_t)b});
+    return id;
+  }
+};
+
+}  // namespace
+
+fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, const void* coeffs,
+                        int64_t batch, int32_t domain, uint64_t modulus, const fpe_scheme* fs,
+                        fpe_tree** out) {
+  if (!out) return fail(FPE_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (nvars < 1 || nvars > 8) return fail(FPE_EINVAL, "nvars must be in 1..8");
+  if (nterms < 1) return fail(FPE_EINVAL, "nterms must be >= 1");
+  if (!exps || !coeffs || !fs) return fail(FPE_EINVAL, "NULL exps, coeffs or scheme");
+  if (domain != FPE_F64 && domain != FPE_F32C && domain != FPE_MODP)
+    return fail(FPE_EINVAL, "unknown domain");
+  if (batch < 1) return fail(FPE_EINVAL, "batch must be >= 1");
+  if (domain != FPE_MODP && batch != 1) return fail(FPE_EINVAL, "batch > 1 needs FPE_MODP");
+  if (domain == FPE_MODP && modulus != kP61 && modulus != kP31)
+    return fail(FPE_EUNSUPPORTED, "modulus must be 2^61-1 or 2^31-1");
+  if (domain == FPE_MODP && batch > 1 && modulus != kP31)
+    return fail(FPE_EINVAL, "a batch of polynomials is compiled for composition mod 2^31-1");
+  Scheme f{fs->kind, fs->threshold, {}};
+  if (fs->kind < FPE_DIRECT || fs->kind > FPE_TABLE) return fail(FPE_EINVAL, "unknown scheme");
+  if (fs->kind == FPE_TABLE) {
+    if (!fs->table || fs->table_len < 2) return fail(FPE_EINVAL, "scheme table is empty");
+    f.table.assign(fs->table, fs->table + fs->table_len);
+    for (int32_t n = 1; n < fs->table_len; ++n)
+      if (f.table[n] < 1 || f.table[n] > n)
+        return fail(FPE_EINVAL, "scheme table entry f(" + std::to_string(n) + ") outside [1, n]");
+  }
+
+  // ---- validate and keep the nonzero terms
+  const double* cf = (const double*)coeffs;
+  const uint64_t* cu = (const uint64_t*)coeffs;
+  std::vector<int64_t> keep;
+  keep.reserve(nterms);
+  for (int64_t t = 0; t < nterms; ++t) {
+    for (int j = 0; j < nvars; ++j) {
+      int32_t v = exps[t * nvars + j];
+      if (v < 0 || v >= (1 << 20)) return fail(FPE_EINVAL, "exponent outside [0, 2^20)");
+    }
+    bool nz = false;
+    if (domain == FPE_MODP) {
+      for (int64_t r = 0; r < batch; ++r) {
+        uint64_t c = cu[r * nterms + t];
+        if (c >= modulus) return fail(FPE_EINVAL, "residue >= modulus");
+        nz |= c != 0;
+      }
+    } else {
+      if (!std::isfinite(cf[t])) return fail(FPE_EINVAL, "non-finite coefficient");
+      nz = cf[t] != 0.0;
+    }
+    if (nz) keep.push_back(t);
+  }
+  if (keep.empty()) return fail(FPE_EINVAL, "the polynomial is zero");
+
+  // ---- order <_t: decreasing lexicographic order of the monomials
+  std::sort(keep.begin(), keep.end(), [&](int64_t x, int64_t y) {
+    for (int j = 0; j < nvars; ++j) {
+      int32_t a = exps[x * nvars + j], b = exps[y * nvars + j];
+      if (a != b) return a > b;
+    }
+    return x < y;
+  });
+  int64_t T = (int64_t)keep.size();
+  std::vector<int32_t> E(T * nvars);
+  for (int64_t t = 0; t < T; ++t)
+    for (int j = 0; j < nvars; ++j) E[t * nvars + j] = exps[keep[t] * nvars + j];
+  for (int64_t t = 1; t < T; ++t)
+    if (std::memcmp(&E[(t - 1) * nvars], &E[t * nvars], sizeof(int32_t) * nvars) == 0)
+      return fail(FPE_EINVAL, "duplicate monomial");
+
+  // ---- tree
+  Builder B{nvars, E, f, T, {}, {}, {}, {}};
+  if (!B.build()) return fail(FPE_EINVAL, B.err);
+  int64_t N = T + (int64_t)B.jexps.size();
+  auto ex_of = [&](int64_t id) -> const int32_t* {
+    return id < T ? &E[id * nvars] : B.jexps[id - T].data();
+  };
+  std::vector<int64_t> order(N);
+  std::iota(order.begin(), order.end(), 0);
+  std::sort(order.begin(), order.end(), [&](int64_t x, int64_t y) {
+    const int32_t* a = ex_of(x);
+    const int32_t* b = ex_of(y);
+    for (int j = 0; j < nvars; ++j)
+      if (a[j] != b[j]) return a[j] > b[j];
+    return false;
+  });
+  std::vector<int64_t> pos(N);
+  for (int64_t i = 0; i < N; ++i) pos[order[i]] = i;
+
+  auto* t = new fpe_tree();
+  t->nvars = nvars;
+  t->domain = domain;
+  t->modulus = domain == FPE_MODP ? modulus : 0;
+  t->batch = batch;
+  t->n_terms = T;
+  t->nodes.resize(N);
+  t->exps.resize(N * nvars);
+  std::vector<int64_t> par(N, -1);
+  int64_t roots = 0;
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t id = order[i];
+    std::memcpy(&t->exps[i * nvars], ex_of(id), sizeof(int32_t) * nvars);
+    par[i] = B.parent[id] < 0 ? -1 : pos[B.parent[id]];
+    roots += par[i] < 0;
+  }
+  if (roots != 1 || par[N - 1] != -1) {
+    delete t;
+    return fail(FPE_EINVAL, "internal: the tree does not have the root last");
+  }
+  std::vector<std::vector<int32_t>> ch(N);
+  for (int64_t i = 0; i < N - 1; ++i) {
+    if (par[i] <= i) {
+      delete t;
+      return fail(FPE_EINVAL, "internal: <_t is not topological");
+    }
+    ch[par[i]].push_back((int32_t)i);   // ascending index = C_1 first
+  }
+
+  // coefficients in node order (junctions 0)
+  std::vector<double> cnode(N, 0.0);
+  if (domain == FPE_MODP) t->coef_rows.assign(batch * N, 0);
+  for (int64_t id = 0; id < T; ++id) {
+    int64_t i = pos[id];
+    if (domain == FPE_MODP) {
+      for (int64_t r = 0; r < batch; ++r) t->coef_rows[r * N + i] = cu[r * nterms + keep[id]];
+    } else {
+      cnode[i] = cf[keep[id]];
+    }
+  }
+
+  // ---- node array: partial degrees, flags, slots, lazy heights, subtrees
+  std::vector<int32_t> H(N, 0), lh(N, 0), slot(N, 0);
+  std::vector<int64_t> sub(N);
+  for (int64_t i = 0; i < N; ++i) {
+    fpe_node& nd = t->nodes[i];
+    std::memset(&nd, 0, sizeof nd);
+    if (domain == FPE_MODP) nd.coef.u = t->coef_rows[i];
+    else nd.coef.f = cnode[i];
+    nd.parent = (int32_t)par[i];
+    const int32_t* me = &t->exps[i * nvars];
+    int nz = 0;
+    for (int j = 0; j < nvars; ++j) {
+      int32_t d = me[j] - (par[i] >= 0 ? t->exps[par[i] * nvars + j] : 0);
+      if (d < 0) {
+        delete t;
+        return fail(FPE_EINVAL, "internal: negative partial degree");
+      }
+      if (d) {
+        ++nz;
+        nd.var = (uint8_t)j;
+        nd.pdeg = d;
+      }
+    }
+    if (nz > 1 || (par[i] >= 0 && nz == 0)) {
+      delete t;
+      return fail(FPE_EINVAL, "internal: partial degree with more than one variable");
+    }
+    if (ch[i].empty()) nd.flags |= FPE_NODE_LEAF;
+    if (order[i] >= T) nd.flags |= FPE_NODE_JUNCTION;
+    if (par[i] < 0) nd.flags |= FPE_NODE_ROOT;
+    else if (ch[par[i]].front() == i) nd.flags |= FPE_NODE_FIRST_CHILD;
+    sub[i] = i;
+    for (int32_t c : ch[i]) sub[i] = std::min(sub[i], sub[c]);
+    if (ch[i].size() >= 2) {
+      int32_t mh = 0, ml = 0;
+      for (size_t k = 1; k < ch[i].size(); ++k) {
+        mh = std::max(mh, H[ch[i][k]]);
+        ml = std::max(ml, lh[ch[i][k]]);
+      }
+      slot[i] = 1 + mh;
+      lh[i] = 1 + ml;
+    }
+    H[i] = slot[i];
+    for (int32_t c : ch[i]) H[i] = std::max(H[i], H[c]);
+    nd.slot = (uint8_t)std::min(slot[i], 255);
+    nd.lazy_height = (uint8_t)std::min(lh[i], 255);
+    nd.sub_begin = (int32_t)sub[i];
+    t->max_slot = std::max(t->max_slot, slot[i]);
+    t->max_lh = std::max(t->max_lh, lh[i]);
+  }
+  // subtrees are contiguous ranges [sub_begin, i]
+  for (int64_t i = 0; i < N; ++i) {
+    int64_t cnt = 1;
+    for (int32_t c : ch[i]) cnt += (c - sub[c] + 1);
+    if (cnt != i - sub[i] + 1) {
+      delete t;
+      return fail(FPE_EINVAL, "internal: subtree is not contiguous");
+    }
+  }
+
+  // ---- power usage
+  std::map<std::pair<int32_t, int32_t>, int64_t> freq;
+  for (int64_t i = 0; i < N; ++i) {
+    const fpe_node& nd = t->nodes[i];
+    if (nd.pdeg > 0) freq[{nd.var, nd.pdeg}] += 1;
+  }
+  t->n_powers = (int32_t)freq.size();
+  std::vector<std::pair<int64_t, std::pair<int32_t, int32_t>>> byf;
+  for (auto& kv : freq) byf.push_back({kv.second, kv.first});
+  std::stable_sort(byf.begin(), byf.end(), [](auto& a, auto& b) { return a.first > b.first; });
+  // largest prefix of the most used powers whose chain fits the table
+  PowerPlan plan;
+  size_t take = byf.size();
+  for (;;) {
+    plan = PowerPlan();
+    for (size_t k = 0; k < take && plan.ok; ++k)
+      plan.ensure(byf[k].second.first, byf[k].second.second, kMaxTable);
+    if (plan.ok) break;
+    --take;
+  }
+  // renumber: used entries by frequency first, chain temporaries after
+  std::vector<int32_t> rank(plan.entries.size(), -1);
+  int32_t nr = 0;
+  for (size_t k = 0; k < take; ++k) rank[plan.index[byf[k].second]] = nr++;
+  for (size_t id = 0; id < plan.entries.size(); ++id)
+    if (rank[id] < 0) rank[id] = nr++;
+  t->n_table = (int32_t)plan.entries.size();
+  t->table_var.assign(t->n_table, 0);
+  t->table_deg.assign(t->n_table, 0);
+  for (size_t id = 0; id < plan.entries.size(); ++id) {
+    t->table_var[rank[id]] = plan.entries[id].first;
+    t->table_deg[rank[id]] = plan.entries[id].second;
+  }
+  for (auto s : plan.chain) {
+    ChainStep c = s;
+    c.dst = (uint8_t)rank[s.dst];
+    if (s.kind == kChainMul) {
+      c.s1 = (uint8_t)rank[s.s1];
+      c.s2 = (uint8_t)rank[s.s2];
+    }
+    t->chain.push_back(c);
+  }
+  auto pidx_of = [&](const fpe_node& nd) -> uint32_t {
+    auto it = plan.index.find({nd.var, nd.pdeg});
+    return it == plan.index.end() ? kOffTable : (uint32_t)rank[it->second];
+  };
+
+  // ---- walk program (stack form of the walk of Section 2.1)
+  auto bits = [&](int64_t i) -> uint64_t {
+    if (domain == FPE_MODP) return t->coef_rows[i];
+    uint64_t u;
+    std::memcpy(&u, &cnode[i], 8);
+    return u;
+  };
+  int32_t depth = 0, maxd = 0;
+  t->ops64.reserve(N);
+  for (int64_t i = 0; i < N; ++i) {
+    const fpe_node& nd = t->nodes[i];
+    OpF64 op{};
+    uint32_t pidx = nd.pdeg > 0 ? pidx_of(nd) : kOffTable;
+    if (nd.pdeg > 0 && pidx == kOffTable) t->n_offtable++;
+    uint32_t info = (pidx << 8) | ((uint32_t)nd.var << 16);
+    op.deg = (uint32_t)nd.pdeg;
+    if (par[i] < 0) {
+      info |= kEnd;
+      if (ch[i].empty()) {
+        info |= kEndLeafRoot;
+        op.a = bits(i);
+      }
+      if (nd.pdeg > 0) info |= kEndHasPow;
+      if (depth != (ch[i].empty() ? 0 : 1)) {
+        delete t;
+        return fail(FPE_EINVAL, "internal: walk stack unbalanced at the root");
+      }
+    } else {
+      bool leaf = ch[i].empty();
+      bool first = (nd.flags & FPE_NODE_FIRST_CHILD) != 0;
+      if (leaf && first) {
+        info |= kLeafOpen;
+        op.a = bits(i);
+        op.b = bits(par[i]);
+        ++depth;
+      } else if (leaf) {
+        info |= kLeafAdd;
+        op.a = bits(i);
+      } else if (first) {
+        info |= kNodeOpen;
+        op.b = bits(par[i]);
+      } else {
+        info |= kNodeAdd;
+        --depth;
+      }
+      maxd = std::max(maxd, depth);
+    }
+    op.info = info;
+    t->ops64.push_back(op);
+  }
+  t->depth = std::max(maxd, 1);
+  if (domain == FPE_F32C) {
+    t->ops32.resize(N);
+    for (int64_t i = 0; i < N; ++i) {
+      const OpF64& o = t->ops64[i];
+      OpF32 q{};
+      double a, b;
+      std::memcpy(&a, &o.a, 8);
+      std::memcpy(&b, &o.b, 8);
+      split_f32(a, q.ah, q.al);
+      split_f32(b, q.bh, q.bl);
+      q.aabs = abs_up(a);
+      q.babs = abs_up(b);
+      q.info = o.info;
+      q.deg = o.deg;
+      t->ops32[i] = q;
+    }
+  }
+  *out = t;
+  return FPE_OK;
+}
+
+}  // namespace fpe

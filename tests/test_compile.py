@@ -1,0 +1,193 @@
+"""Host compiler (fpe_compile through the C-ABI) against the oracle's own,
+independent tree builder, and the boundary's error behaviour.  No GPU."""
+import json
+import os
+import re
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+import paper_1307_5655_amd as fpe
+from oracle import schemes, tree
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+ORACLE_SCHEMES = {"direct": schemes.direct, "horner": schemes.horner, "estrin": schemes.estrin,
+                  "balanced": schemes.balanced, "balanced_floor": schemes.balanced_literal}
+
+
+def lib_tree(terms, scheme, domain=fpe.F64):
+    ex = np.array([m for m, _ in terms], dtype=np.int32)
+    co = np.array([c for _, c in terms], dtype=np.float64)
+    return fpe.Tree(ex, co, scheme, domain)
+
+
+def compare(terms, scheme):
+    t = lib_tree(terms, scheme)
+    nodes = t.nodes()
+    exps = t.node_exps()
+    o = tree.build_tree(terms, ORACLE_SCHEMES[scheme])
+    assert len(o) == len(nodes)
+    lh = tree.lazy_heights(o)
+    ss = tree.safe_slots(o)
+    for i, on in enumerate(o):
+        assert tuple(exps[i]) == on.exps
+        p = nodes["parent"][i]
+        if on.parent is None:
+            assert p == -1 and nodes["flags"][i] & fpe.NODE_ROOT
+        else:
+            assert p == on.parent.index
+            first = on.parent.children[0] is on
+            assert bool(nodes["flags"][i] & fpe.NODE_FIRST_CHILD) == first
+        assert bool(nodes["flags"][i] & fpe.NODE_LEAF) == (not on.children)
+        assert bool(nodes["flags"][i] & fpe.NODE_JUNCTION) == on.junction
+        nz = [(j, e) for j, e in enumerate(on.pdeg) if e]
+        if nz:
+            assert (nodes["var"][i], nodes["pdeg"][i]) == nz[0]
+        else:
+            assert nodes["pdeg"][i] == 0
+        assert nodes["slot"][i] == ss[i]
+        assert nodes["lazy_height"][i] == lh[i]
+        # subtree = [sub_begin, i]
+        lo = i
+        stack = [on]
+        while stack:
+            n = stack.pop()
+            lo = min(lo, n.index)
+            stack.extend(n.children)
+        assert nodes["sub_begin"][i] == lo
+    return t
+
+
+@pytest.mark.parametrize("scheme", ["direct", "horner", "estrin", "balanced", "balanced_floor"])
+def test_worked_example_matches_golden(scheme):
+    with open(os.path.join(ROOT, "tests", "golden", "worked_example.json")) as f:
+        g = json.load(f)
+    c = g["coeffs_by_exponent"]
+    terms = [((e,), float(v)) for e, v in enumerate(c) if v]
+    t = compare(terms, scheme)
+    if scheme in g["children_by_exponent"]:
+        nodes = t.nodes()
+        exps = t.node_exps()[:, 0]
+        ch = {}
+        for i, p in enumerate(nodes["parent"]):
+            if p >= 0:
+                ch.setdefault(str(exps[p]), []).append(int(exps[i]))
+        assert ch == g["children_by_exponent"][scheme]
+
+
+poly_uni = st.dictionaries(st.integers(0, 300), st.integers(-9, 9).filter(lambda v: v != 0),
+                           min_size=1, max_size=80)
+
+
+@settings(max_examples=80, deadline=None)
+@given(poly_uni, st.sampled_from(["direct", "horner", "estrin", "balanced", "balanced_floor"]))
+def test_univariate_trees_match_oracle(d, scheme):
+    compare([((e,), float(c)) for e, c in d.items()], scheme)
+
+
+poly_multi = st.integers(1, 4).flatmap(lambda v: st.dictionaries(
+    st.tuples(*[st.integers(0, 7)] * v), st.integers(-5, 5).filter(lambda c: c != 0),
+    min_size=1, max_size=60))
+
+
+@settings(max_examples=80, deadline=None)
+@given(poly_multi, st.sampled_from(["horner", "estrin", "balanced", "direct"]))
+def test_multivariate_trees_match_oracle(d, scheme):
+    compare([(m, float(c)) for m, c in d.items()], scheme)
+
+
+@pytest.mark.parametrize("n", [1023, 3000, 5000])
+def test_config_sized_trees_match_oracle(n):
+    import fpe_inputs
+    inp = fpe_inputs.sparse_uni(n, npts=1)
+    ex, co = inp.terms()
+    for scheme in ["horner", "estrin", "balanced"]:
+        compare([((int(e[0]),), float(c)) for e, c in zip(ex, co)], scheme)
+
+
+def test_trivariate_dense_shape():
+    import fpe_inputs
+    inp = fpe_inputs.trivariate(npts=1)
+    t = fpe.Tree(inp.exps, inp.coeffs, "estrin", fpe.MODP, fpe.P61)
+    assert t.info.n_nodes == 12341 and t.info.n_terms == 12341   # no junction
+    nodes = t.nodes()
+    assert not np.any(nodes["flags"] & fpe.NODE_JUNCTION)
+
+
+def test_threshold_and_table_schemes():
+    rng = np.random.default_rng(4)
+    c = rng.uniform(-1, 1, 200)
+    ex = np.arange(200, dtype=np.int32).reshape(-1, 1)
+    t = fpe.Tree(ex, c, "threshold", threshold=10)
+    o = tree.build_tree(tree.dense_terms(c), schemes.threshold(10))
+    assert [tuple(r) for r in t.node_exps()] == [n.exps for n in o]
+    tab = [0] + [max(1, k // 3) for k in range(1, 400)]
+    t = fpe.Tree(ex, c, "table", table=tab)
+    o = tree.build_tree(tree.dense_terms(c), schemes.table(tab))
+    par = t.nodes()["parent"]
+    assert [p for p in par] == [n.parent.index if n.parent else -1 for n in o]
+
+
+def test_errors_are_status_codes():
+    ex = np.array([[0], [1]], dtype=np.int32)
+    with pytest.raises(fpe.FpeError) as e:
+        fpe.Tree(np.array([[1], [1]], dtype=np.int32), [1.0, 2.0], "horner")
+    assert e.value.status == -1 and "duplicate" in str(e.value)
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree(ex, [0.0, 0.0], "horner")                      # zero polynomial
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree(ex, [1.0, float("nan")], "horner")             # non-finite
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree(np.array([[-1]], dtype=np.int32), [1.0], "horner")
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree(ex, [1, fpe.P61], "horner", fpe.MODP, fpe.P61)  # residue >= p
+    with pytest.raises(fpe.FpeError) as e:
+        fpe.Tree(ex, [1, 2], "horner", fpe.MODP, 1000003)
+    assert e.value.status == -5
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree(np.zeros((2, 9), dtype=np.int32), [1.0, 2.0], "horner")   # nvars > 8
+    with pytest.raises(fpe.FpeError) as e:
+        fpe.Tree(np.arange(20, dtype=np.int32).reshape(-1, 1), np.ones(20), "table",
+                 table=[0, 1, 2, 5])                             # f(3) = 5 > 3
+    assert "outside" in str(e.value)
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree(np.arange(20, dtype=np.int32).reshape(-1, 1), np.ones(20), "table",
+                 table=[0, 1, 1])                                # f(19) missing
+    t = fpe.Tree(ex, [1.0, 2.0], "horner")
+    with pytest.raises(fpe.FpeError):                            # not uploaded
+        import ctypes
+        fpe._check(fpe.lib.fpe_evaluate(t.handle, None, 1, None, None, None))
+
+
+def test_zero_coefficients_dropped_and_single_term():
+    t = fpe.Tree(np.array([[5], [3], [0]], dtype=np.int32), [2.0, 0.0, 0.0], "estrin")
+    nodes = t.nodes()
+    assert len(nodes) == 1 and nodes["pdeg"][0] == 5 and nodes["flags"][0] & fpe.NODE_ROOT
+
+
+def test_serialize_roundtrip():
+    rng = np.random.default_rng(6)
+    ex = np.unique(rng.integers(0, 9, size=(50, 3)), axis=0).astype(np.int32)
+    co = rng.uniform(-1, 1, len(ex))
+    t = fpe.Tree(ex, co, "balanced", fpe.F32C)
+    blob = t.serialize()
+    t2 = fpe.Tree.deserialize(blob, fpe.F32C)
+    assert t2.serialize() == blob
+    assert np.array_equal(t2.nodes(), t.nodes())
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree.deserialize(blob[:-3])
+    bad = bytearray(blob)
+    bad[0] ^= 0xFF
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree.deserialize(bytes(bad))
+
+
+def test_library_exports_every_declared_symbol():
+    hdr = open(os.path.join(ROOT, "include", "fpe.h")).read()
+    names = set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(fpe_\w+)\s*\(", hdr, flags=re.M))
+    assert len(names) >= 20
+    for n in sorted(names):
+        assert hasattr(fpe.lib, n), n
+    assert set(fpe.EXPORTED) <= names
+    assert fpe.lib.fpe_version().decode().startswith("fpe")

@@ -1,0 +1,233 @@
+"""GPU parity: the HIP walk (through the C-ABI) against the CPU oracle.
+
+Floating point: plain FP64 within 1e-13 of the oracle scaled by the condition
+sum ptilde(|x|) = sum |c_m| |x|^m (the relative error divided by the
+condition number); compensated FP32 (with the FP64 fallback) within 1e-12
+relative error at every point.  Mod 2^61 - 1: bit-exact."""
+import numpy as np
+import pytest
+import torch
+
+import fpe_inputs
+import paper_1307_5655_amd as fpe
+from oracle import exact, native
+
+pytestmark = pytest.mark.gpu
+
+TOL_F64 = 1e-13
+TOL_F32C = 1e-12
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def to_dev(a, dev):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+
+
+def eval_uni(coeffs, x, scheme, domain, dev, **kw):
+    e = np.nonzero(coeffs)[0].astype(np.int32).reshape(-1, 1)
+    t = fpe.Tree(e, coeffs[e[:, 0]], scheme, domain).upload(dev)
+    y = fpe.evaluate(t, [to_dev(x, dev)], **kw)
+    torch.cuda.synchronize()
+    return y.cpu().numpy(), t
+
+
+def check_f64(y, coeffs, x):
+    ref = native.dd_value(coeffs, x)
+    pt = native.ptilde(coeffs, x)
+    err = np.abs(y - ref) / pt
+    assert np.all(np.isfinite(y))
+    assert err.max() <= TOL_F64, f"max scaled error {err.max():.3e}"
+    return err
+
+
+def check_f32c(y, coeffs, x):
+    ref = native.dd_value(coeffs, x)
+    rel = np.abs(y - ref) / np.abs(ref)
+    bad = ~(rel <= TOL_F32C)
+    assert not bad.any(), f"{bad.sum()} points above 1e-12, worst {np.nanmax(rel):.3e} at x={x[bad][:4]}"
+    return rel
+
+
+@pytest.mark.parametrize("scheme", ["horner", "estrin", "balanced", "direct"])
+def test_dense_1023_f64(dev, scheme):
+    say(f"dense n=1023 f64 {scheme}")
+    inp = fpe_inputs.dense_uni(npts=20_000 + 37)       # ragged tail
+    y, _ = eval_uni(inp.coeffs, inp.points, scheme, fpe.F64, dev)
+    check_f64(y, inp.coeffs, inp.points)
+
+
+def test_dense_horner_bit_identical_to_fma_horner(dev):
+    say("dense n=1023 horner bit-exact")
+    inp = fpe_inputs.dense_uni(npts=5000)
+    y, _ = eval_uni(inp.coeffs, inp.points, "horner", fpe.F64, dev)
+    want = native.horner_f64(inp.coeffs, inp.points, use_fma=True)
+    assert np.array_equal(y, want)
+
+
+@pytest.mark.parametrize("n", [3000, 5000])
+@pytest.mark.parametrize("scheme", ["horner", "estrin", "balanced"])
+def test_sparse_f64(dev, n, scheme):
+    say(f"sparse n={n} f64 {scheme}")
+    inp = fpe_inputs.sparse_uni(n, npts=8_000 + 13)
+    y, _ = eval_uni(inp.coeffs, inp.points, scheme, fpe.F64, dev)
+    check_f64(y, inp.coeffs, inp.points)
+
+
+@pytest.mark.parametrize("n", [3000, 5000])
+@pytest.mark.parametrize("scheme", ["horner", "estrin", "balanced"])
+def test_sparse_f32c(dev, n, scheme):
+    say(f"sparse n={n} f32c {scheme}")
+    inp = fpe_inputs.sparse_uni(n, npts=8_000 + 13)
+    nfb = torch.zeros(1, dtype=torch.int64, device=dev)
+    cond = torch.empty(len(inp.points), dtype=torch.float32, device=dev)
+    y, _ = eval_uni(inp.coeffs, inp.points, scheme, fpe.F32C, dev, nfallback_out=nfb, cond_out=cond)
+    check_f32c(y, inp.coeffs, inp.points)
+    frac = nfb.item() / len(inp.points)
+    say(f"  fallback fraction {frac:.4f}")
+    # points beyond the FP32 range of x^n must have been re-evaluated
+    assert frac >= np.mean(np.abs(inp.points) > 1.04) - 1e-9
+
+
+def test_f32c_forced_modes(dev):
+    say("f32c forced fallback / none")
+    inp = fpe_inputs.sparse_uni(3000, npts=3000, lo=-0.99, hi=0.99)
+    y_all, _ = eval_uni(inp.coeffs, inp.points, "balanced", fpe.F32C, dev, force=1)
+    check_f32c(y_all, inp.coeffs, inp.points)
+    y_none, _ = eval_uni(inp.coeffs, inp.points, "balanced", fpe.F32C, dev, force=2)
+    ref = native.dd_value(inp.coeffs, inp.points)
+    pt = native.ptilde(inp.coeffs, inp.points)
+    # without any fallback the double-float walk is still accurate to ~1e-13 ptilde
+    assert np.max(np.abs(y_none - ref) / pt) < 1e-12
+
+
+def test_f32c_cond_and_flags(dev):
+    say("f32c cond + flags")
+    inp = fpe_inputs.sparse_uni(1000, npts=4096 + 5)
+    n = len(inp.points)
+    cond = torch.empty(n, dtype=torch.float32, device=dev)
+    flags = torch.zeros((n + 31) // 32 + 2, dtype=torch.int32, device=dev)
+    nfb = torch.zeros(1, dtype=torch.int64, device=dev)
+    y, _ = eval_uni(inp.coeffs, inp.points, "estrin", fpe.F32C, dev, cond_out=cond, flags_out=flags,
+                    nfallback_out=nfb)
+    ref = native.dd_value(inp.coeffs, inp.points)
+    pt = native.ptilde(inp.coeffs, inp.points)
+    c = cond.cpu().numpy()
+    want = pt / np.abs(ref)
+    ok = np.isfinite(c) & (want < 1e6)
+    assert np.allclose(c[ok], want[ok], rtol=1e-3)
+    bits = np.unpackbits(flags.cpu().numpy().view(np.uint8), bitorder="little")[:n]
+    assert bits.sum() == nfb.item()
+
+
+def test_edge_cases_f64(dev):
+    say("edge cases")
+    # single term, constant, zero constant term (root with a power), x = 0, +-1
+    x = np.array([0.0, 1.0, -1.0, 0.5, -2.0, 1e-3], dtype=np.float64)
+    cases = [
+        ({7: 3.0}, None),
+        ({0: -2.5}, None),
+        ({3: 1.0, 5: -2.0, 9: 0.25}, None),
+        ({0: 1.0, 1: 1.0}, None),
+    ]
+    for d, _ in cases:
+        e = np.array(sorted(d), dtype=np.int32).reshape(-1, 1)
+        c = np.array([d[k] for k in sorted(d)])
+        dense = np.zeros(max(d) + 1)
+        for k, v in d.items():
+            dense[k] = v
+        for scheme in ["horner", "estrin", "balanced", "direct"]:
+            for dom in (fpe.F64, fpe.F32C):
+                t = fpe.Tree(e, c, scheme, dom).upload(dev)
+                y = fpe.evaluate(t, [to_dev(x, dev)]).cpu().numpy()
+                ye = np.array([float(exact.exact_value([((k,), v) for k, v in d.items()], [xi])) for xi in x])
+                assert np.allclose(y, ye, rtol=1e-14, atol=0), (d, scheme, dom, y, ye)
+    # empty input
+    t = fpe.Tree(np.array([[1]], dtype=np.int32), [1.0], "horner").upload(dev)
+    out = torch.empty(0, dtype=torch.float64, device=dev)
+    fpe.evaluate(t, [torch.empty(0, dtype=torch.float64, device=dev)], out=out)
+    torch.cuda.synchronize()
+
+
+def test_multivariate_f64_and_f32c(dev):
+    say("multivariate f64 / f32c with junctions")
+    g = np.random.default_rng([13075655, 77])
+    for v, T in [(2, 300), (3, 1500), (4, 400)]:
+        m = fpe_inputs.random_multi_f64(v, T, 3000 + 7, g)
+        for scheme in ["horner", "estrin", "balanced"]:
+            ref = exact.dd_monomial_sum(m.exps, m.coeffs, m.points)
+            pt = exact.monomial_ptilde(m.exps, m.coeffs, m.points)
+            for dom in (fpe.F64, fpe.F32C):
+                t = fpe.Tree(m.exps, m.coeffs, scheme, dom).upload(dev)
+                y = fpe.evaluate(t, [to_dev(m.points[j], dev) for j in range(v)]).cpu().numpy()
+                if dom == fpe.F64:
+                    err = np.abs(y - ref) / pt
+                    assert err.max() <= TOL_F64, (v, scheme, err.max())
+                else:
+                    rel = np.abs(y - ref) / np.abs(ref)
+                    assert rel.max() <= TOL_F32C, (v, scheme, rel.max())
+
+
+@pytest.mark.parametrize("scheme", ["horner", "estrin", "balanced"])
+def test_trivariate_modp_bit_exact(dev, scheme):
+    say(f"trivariate mod p {scheme}")
+    inp = fpe_inputs.trivariate(npts=2000 + 3)
+    t = fpe.Tree(inp.exps, inp.coeffs, scheme, fpe.MODP, fpe.P61).upload(dev)
+    pts = [to_dev(inp.points[j].view(np.int64), dev) for j in range(3)]
+    y = fpe.evaluate(t, pts).cpu().numpy().view(np.uint64)
+    want = native.modp_eval(inp.exps, inp.coeffs, fpe.P61, inp.points)
+    assert np.array_equal(y, want)
+
+
+def test_sparse_multivariate_modp_bit_exact(dev):
+    say("sparse multivariate mod p with junctions")
+    for v, T, D in [(2, 200, 30), (3, 800, 25), (4, 300, 12)]:
+        m = fpe_inputs.random_modp_poly(v, T, D, 1000 + 1, seed=(v,))
+        for scheme in ["horner", "estrin", "balanced", "direct"]:
+            t = fpe.Tree(m.exps, m.coeffs, scheme, fpe.MODP, fpe.P61).upload(dev)
+            y = fpe.evaluate(t, [to_dev(m.points[j].view(np.int64), dev) for j in range(v)])
+            y = y.cpu().numpy().view(np.uint64)
+            want = native.modp_eval(m.exps, m.coeffs, fpe.P61, m.points)
+            assert np.array_equal(y, want), (v, scheme)
+
+
+# ----------------------------------------------------------------------------
+# full sizes, in the launch configuration the benchmark times, sampled
+# ----------------------------------------------------------------------------
+
+@pytest.mark.parametrize("n", [3000, 5000])
+def test_full_size_sparse_sampled(dev, n):
+    say(f"full size sparse n={n}, 1e7 points, sampled")
+    inp = fpe_inputs.sparse_uni(n)
+    x = to_dev(inp.points, dev)
+    rng = np.random.default_rng(n)
+    idx = np.sort(rng.choice(len(inp.points), 3000, replace=False))
+    idx[-1] = len(inp.points) - 1
+    e, c = inp.terms()
+    for scheme in ["horner", "estrin", "balanced"]:
+        for dom in (fpe.F64, fpe.F32C):
+            say(f"  {scheme} {dom}")
+            t = fpe.Tree(e, c, scheme, dom).upload(dev)
+            y = fpe.evaluate(t, [x])
+            torch.cuda.synchronize()
+            ys = y.cpu().numpy()[idx]
+            if dom == fpe.F64:
+                check_f64(ys, inp.coeffs, inp.points[idx])
+            else:
+                check_f32c(ys, inp.coeffs, inp.points[idx])
+            del y
+
+
+def test_full_size_trivariate_sampled(dev):
+    say("full size trivariate mod p, 1e6 points, sampled")
+    inp = fpe_inputs.trivariate()
+    pts = [to_dev(inp.points[j].view(np.int64), dev) for j in range(3)]
+    rng = np.random.default_rng(3)
+    idx = np.sort(rng.choice(inp.points.shape[1], 500, replace=False))
+    want = native.modp_eval(inp.exps, inp.coeffs, fpe.P61, np.ascontiguousarray(inp.points[:, idx]))
+    for scheme in ["horner", "estrin", "balanced"]:
+        t = fpe.Tree(inp.exps, inp.coeffs, scheme, fpe.MODP, fpe.P61).upload(dev)
+        y = fpe.evaluate(t, pts).cpu().numpy().view(np.uint64)
+        assert np.array_equal(y[idx], want), scheme
