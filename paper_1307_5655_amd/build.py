@@ -8,8 +8,9 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfpe.so")
-SOURCES = ["compile.cpp", "api.cpp", "walk.hip"]
-EXTRA_SOURCES = ["compose.hip", "server.cpp"]
+SOURCES = ["compile.cpp", "api.cpp", "walk.hip", "eval_f64.hip", "eval_m61.hip", "eval_df32.hip",
+           "serve_kernels.hip", "compose.hip", "server.cpp"]
+EXTRA_SOURCES = []
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
@@ -17,6 +18,9 @@ FLAGS = [
     # error-free transforms (TwoSum, TwoProd) must not be contracted: every
     # intended fused multiply-add is written as an explicit builtin
     "-ffp-contract=off",
+    # the walk's branches are wave-uniform: leave them unstructurised so the
+    # accumulators are not copied through flow blocks on every op
+    "-mllvm", "-structurizecfg-skip-uniform-regions=true",
     # packed FP32 VALU instructions are disabled on purpose
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", "-I", os.path.join(HERE, "..", "include"),

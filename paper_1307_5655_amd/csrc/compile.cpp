@@ -441,7 +441,11 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
   };
 
   // ---- walk program (stack form of the walk of Section 2.1)
+  // A batch tree (composition) keeps its coefficients per instance, so its
+  // ops carry node indices instead of coefficient values.
+  const bool index_ops = domain == FPE_MODP && modulus == kP31;
   auto bits = [&](int64_t i) -> uint64_t {
+    if (index_ops) return (uint64_t)i;
     if (domain == FPE_MODP) return t->coef_rows[i];
     uint64_t u;
     std::memcpy(&u, &cnode[i], 8);
@@ -454,10 +458,10 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
     OpF64 op{};
     uint32_t pidx = nd.pdeg > 0 ? pidx_of(nd) : kOffTable;
     if (nd.pdeg > 0 && pidx == kOffTable) t->n_offtable++;
-    uint32_t info = (pidx << 8) | ((uint32_t)nd.var << 16);
+    uint32_t info = (pidx << 8) | ((uint32_t)nd.var << 16) | ((uint32_t)std::min(depth, 31) << 20);
     op.deg = (uint32_t)nd.pdeg;
     if (par[i] < 0) {
-      info |= kEnd;
+      info |= kEnd | kBitEnd;
       if (ch[i].empty()) {
         info |= kEndLeafRoot;
         op.a = bits(i);
@@ -471,15 +475,15 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
       bool leaf = ch[i].empty();
       bool first = (nd.flags & FPE_NODE_FIRST_CHILD) != 0;
       if (leaf && first) {
-        info |= kLeafOpen;
+        info |= kLeafOpen | kBitLeaf | kBitFirst;
         op.a = bits(i);
         op.b = bits(par[i]);
         ++depth;
       } else if (leaf) {
-        info |= kLeafAdd;
+        info |= kLeafAdd | kBitLeaf;
         op.a = bits(i);
       } else if (first) {
-        info |= kNodeOpen;
+        info |= kNodeOpen | kBitFirst;
         op.b = bits(par[i]);
       } else {
         info |= kNodeAdd;

@@ -1,0 +1,96 @@
+// Compensated FP32 (double-float) walk kernel and the FP64 (double-double)
+// re-evaluation of the points it flags.
+#include "walk_core.h"
+
+namespace fpe {
+
+template <int DMAX, int PPL, bool OFFT>
+__global__ __launch_bounds__(kBlock) void k_eval_df32(DevTree tr, Pts<double> P, int64_t npts,
+                                                      F32COut o) {
+  extern __shared__ __align__(16) char lds[];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int64_t base = (int64_t)blockIdx.x * kBlock * PPL + threadIdx.x;
+  double x[PPL][8];
+  load_points<double, PPL>(P, tr.nvars, base, npts, x);
+  DF r[PPL];
+  walk_points<ArDF32, DMAX, PPL, OFFT>(tr, x, lds, r);
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int64_t i = base + (int64_t)j * kWave;
+    bool flag = false;
+    if (i < npts) {
+      double y;
+      float cond;
+      flag = df32_finish(r[j], o.tol, o.force, y, cond);
+      o.out[i] = y;
+      if (o.cond) o.cond[i] = cond;
+    }
+    if (o.flags) {
+      const uint64_t ballot = __ballot(flag);
+      const int64_t wbase = i - lane;
+      if (lane == 0 && wbase < npts) {
+        o.flags[wbase >> 5] = (uint32_t)ballot;
+        if (wbase + 32 < npts) o.flags[(wbase >> 5) + 1] = (uint32_t)(ballot >> 32);
+      }
+    }
+    append_flagged(flag, i, o.list, o.count);
+  }
+}
+
+// FP64 fallback: double-double walk over the flagged points.  The grid is
+// fixed; wavefronts stride over the count read from device memory.
+template <int DMAX, bool OFFT>
+__global__ __launch_bounds__(kBlock) void k_fallback_dd(DevTree tr, Pts<double> P,
+                                                        const int32_t* __restrict__ list,
+                                                        const int64_t* __restrict__ count,
+                                                        double* __restrict__ out) {
+  extern __shared__ __align__(16) char lds[];
+  const int64_t n = *count;
+  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
+    const int64_t k = base + threadIdx.x;
+    double x[8];
+    const int64_t i = k < n ? list[k] : -1;
+#pragma unroll
+    for (int v = 0; v < 8; ++v) x[v] = (i >= 0 && v < tr.nvars) ? P.p[v][i] : 0.0;
+    const DD r = walk_point<ArDD, DMAX, OFFT>(tr, x, lds);
+    if (i >= 0) out[i] = r.h + r.l;
+  }
+}
+
+template <int DMAX, int PPL, bool OFFT>
+static void go(const KernelLaunch& L, const F32COut& o) {
+  Pts<double> P{};
+  for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const double*)L.pts[j];
+  hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), L.lds,
+                     L.stream, L.tr, P, L.npts, o);
+}
+
+void launch_df32(const KernelLaunch& L, const F32COut& o) {
+  const bool d8 = L.tr.depth <= 8;
+  if (L.offt) {
+    if (d8) go<8, 1, true>(L, o); else go<kMaxDepth, 1, true>(L, o);
+  } else if (L.ppl >= 2 && d8) {
+    go<8, 2, false>(L, o);
+  } else {
+    if (d8) go<8, 1, false>(L, o); else go<kMaxDepth, 1, false>(L, o);
+  }
+}
+
+template <int DMAX, bool OFFT>
+static void gofb(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out) {
+  Pts<double> P{};
+  for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const double*)L.pts[j];
+  hipLaunchKernelGGL((k_fallback_dd<DMAX, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), L.lds,
+                     L.stream, L.tr, P, list, count, out);
+}
+
+void launch_fallback(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out) {
+  const bool d8 = L.tr.depth <= 8;
+  if (L.offt) {
+    if (d8) gofb<8, true>(L, list, count, out); else gofb<kMaxDepth, true>(L, list, count, out);
+  } else {
+    if (d8) gofb<8, false>(L, list, count, out); else gofb<kMaxDepth, false>(L, list, count, out);
+  }
+}
+
+}  // namespace fpe

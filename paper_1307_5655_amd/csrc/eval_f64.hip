@@ -1,0 +1,43 @@
+// Plain FP64 walk kernel: one fused multiply-add per node and point.
+#include "walk_core.h"
+
+namespace fpe {
+
+template <int DMAX, int PPL, bool OFFT>
+__global__ __launch_bounds__(kBlock) void k_eval_f64(DevTree tr, Pts<double> P, int64_t npts,
+                                                     double* __restrict__ out) {
+  extern __shared__ __align__(16) char lds[];
+  const int64_t base = (int64_t)blockIdx.x * kBlock * PPL + threadIdx.x;
+  double x[PPL][8];
+  load_points<double, PPL>(P, tr.nvars, base, npts, x);
+  double y[PPL];
+  walk_points<ArF64, DMAX, PPL, OFFT>(tr, x, lds, y);
+#pragma unroll
+  for (int j = 0; j < PPL; ++j) {
+    const int64_t i = base + (int64_t)j * kWave;
+    if (i < npts) out[i] = y[j];
+  }
+}
+
+template <int DMAX, int PPL, bool OFFT>
+static void go(const KernelLaunch& L, double* out) {
+  Pts<double> P{};
+  for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const double*)L.pts[j];
+  hipLaunchKernelGGL((k_eval_f64<DMAX, PPL, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), L.lds,
+                     L.stream, L.tr, P, L.npts, out);
+}
+
+void launch_f64(const KernelLaunch& L, double* out) {
+  const bool d8 = L.tr.depth <= 8;
+  if (L.offt) {
+    if (d8) go<8, 1, true>(L, out); else go<kMaxDepth, 1, true>(L, out);
+  } else if (L.ppl >= 4 && d8) {
+    go<8, 4, false>(L, out);
+  } else if (L.ppl >= 2) {
+    if (d8) go<8, 2, false>(L, out); else go<kMaxDepth, 2, false>(L, out);
+  } else {
+    if (d8) go<8, 1, false>(L, out); else go<kMaxDepth, 1, false>(L, out);
+  }
+}
+
+}  // namespace fpe

@@ -31,15 +31,22 @@ constexpr uint64_t kP31 = (uint64_t(1) << 31) - 1;
 enum OpKind : uint32_t { kLeafAdd = 0, kNodeOpen = 1, kLeafOpen = 2, kNodeAdd = 3, kEnd = 4 };
 
 // info word: bits 0-2 kind, bit 3 root-without-children (END), bit 4 root has
-// a power (END), bits 8-15 power-table index (kOffTable = on the fly),
-// bits 16-19 variable.  deg holds the partial degree (for on-the-fly powers).
+// a power (END), bits 5-7 the kind as flags (leaf / first child / end) for a
+// two-test dispatch, bits 8-15 power-table index (kOffTable = on the fly),
+// bits 16-19 variable, bits 20-24 the stack depth L before the op (so a flat
+// loop can address the accumulators with compile-time indices).  deg holds
+// the partial degree (for on-the-fly powers).
 constexpr uint32_t kOffTable = 255;
 constexpr uint32_t kEndLeafRoot = 1u << 3;
 constexpr uint32_t kEndHasPow = 1u << 4;
+constexpr uint32_t kBitLeaf = 1u << 5;
+constexpr uint32_t kBitFirst = 1u << 6;
+constexpr uint32_t kBitEnd = 1u << 7;
 
 __host__ __device__ inline uint32_t op_kind(uint32_t info) { return info & 7u; }
 __host__ __device__ inline uint32_t op_pidx(uint32_t info) { return (info >> 8) & 255u; }
 __host__ __device__ inline uint32_t op_var(uint32_t info) { return (info >> 16) & 15u; }
+__host__ __device__ inline uint32_t op_level(uint32_t info) { return (info >> 20) & 31u; }
 
 struct alignas(32) OpF64 {   // FP64 / double-double / mod-p walks
   uint64_t a;                // c(N) or c(P): FP64 bits or residue
@@ -84,19 +91,29 @@ struct DevTree {
   int64_t batch;
 };
 
-// Work-table entry of a fused (served) launch: one block of points of one
-// request.
+// Work-table entry of a fused (served) launch: one request.  Its points are
+// cut into 64-point blocks; prefix[r] is the first block of request r in the
+// launch, so a workgroup finds its request by a binary search over prefix.
 struct WorkItem {
   DevTree tree;
   const double* pts[8];
   double* out;
   float* cond;
-  uint32_t* flags;     // fallback bitmask of this request (32 points / word)
-  int64_t begin;       // first point of this block
-  int64_t npts;        // points of the whole request
+  int32_t* list;       // F32C: fallback indices (request workspace)
+  int64_t npts;
   double tol;
   int32_t domain;
   int32_t pad;
+};
+
+// Device-side description of one fused launch (fixed addresses, so that the
+// launch can be replayed from a HIP graph with new contents each batch).
+struct WorkTable {
+  int32_t n_items;
+  int32_t pad;
+  int64_t total_blocks;
+  // followed in memory by: WorkItem items[kMaxServe]; int64_t prefix[kMaxServe + 1];
+  //                         int64_t counters[kMaxServe]
 };
 
 }  // namespace fpe
@@ -138,10 +155,42 @@ size_t eval_workspace_bytes(const fpe_tree* t, int64_t npts);
 fpe_status launch_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out,
                           void* ws, size_t ws_bytes, void* stream);
 size_t compose_workspace_bytes(const fpe_tree* t, int32_t dq);
-// Fused served launch (walk.hip): items in device memory.
-fpe_status launch_work_table(const WorkItem* items_dev, int32_t n_items, int32_t n_f32c,
-                             int64_t* fallback_counter, void* stream);
 constexpr int kMaxDepth = 16;   // stack depth the kernels hold
 constexpr int kMaxTable = 48;   // power-table entries held per point
-constexpr int kServeBlockPts = 256;
+constexpr int kMaxServe = 256;  // requests per fused launch
+constexpr int kServeGrid = 4096;   // fixed grid of the fused kernels (workgroups)
+// Fused served launch (walk.hip).
+struct ServeKernels {
+  const void* zero;       // k_serve_zero(WorkTable*)
+  const void* walk8;      // k_serve_walk<8>(WorkTable*)
+  const void* walk16;     // k_serve_walk<16>(WorkTable*)
+  const void* fallback8;  // k_serve_fallback<8>(WorkTable*)
+  const void* fallback16;
+};
+ServeKernels serve_kernels();
+size_t work_table_bytes();
+__host__ __device__ inline WorkItem* table_items(WorkTable* t) { return (WorkItem*)((char*)t + 256); }
+__host__ __device__ inline int64_t* table_prefix(WorkTable* t) {
+  return (int64_t*)(table_items(t) + kMaxServe);
+}
+__host__ __device__ inline int64_t* table_counters(WorkTable* t) { return table_prefix(t) + kMaxServe + 1; }
+size_t lds_bytes(const fpe_tree* t, int domain);
+
+// One pointwise launch (walk.hip picks the shape; the eval_*.hip files hold
+// the kernels).
+struct KernelLaunch {
+  DevTree tr;
+  const void* pts[8];
+  int64_t npts;
+  int64_t nblocks;
+  size_t lds;
+  hipStream_t stream;
+  int ppl;
+  bool offt;
+};
+struct F32COut;
+void launch_f64(const KernelLaunch& L, double* out);
+void launch_m61(const KernelLaunch& L, uint64_t* out);
+void launch_df32(const KernelLaunch& L, const F32COut& o);
+void launch_fallback(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out);
 }  // namespace fpe

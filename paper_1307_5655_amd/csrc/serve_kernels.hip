@@ -1,0 +1,93 @@
+// Fused served launches: one work table of requests (different trees, point
+// counts and forms) in one launch over a fixed grid that strides over the
+// 64-point blocks of all requests.
+#include "walk_core.h"
+
+namespace fpe {
+
+__device__ __forceinline__ int find_item(const int64_t* __restrict__ prefix, int n, int64_t b) {
+  int lo = 0, hi = n;   // prefix[lo] <= b < prefix[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (prefix[mid] <= b) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+__global__ void k_serve_zero(WorkTable* wt) {
+  const int n = wt->n_items;
+  int64_t* cnt = table_counters(wt);
+  for (int r = threadIdx.x; r < n; r += blockDim.x) cnt[r] = 0;
+}
+
+template <int DMAX>
+__global__ __launch_bounds__(kBlock) void k_serve_walk(WorkTable* wt) {
+  extern __shared__ __align__(16) char lds[];
+  const int n = wt->n_items;
+  const int64_t total = wt->total_blocks;
+  const WorkItem* items = table_items(wt);
+  const int64_t* prefix = table_prefix(wt);
+  int64_t* counters = table_counters(wt);
+  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    const int r = find_item(prefix, n, b);
+    const WorkItem& it = items[r];
+    const int64_t i = (b - prefix[r]) * kBlock + (threadIdx.x & (kWave - 1));
+    const bool in = i < it.npts;
+    double x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = (in && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
+    bool flag = false;
+    if (it.domain == FPE_F64) {
+      const double y = walk_point<ArF64, DMAX, false>(it.tree, x, lds);
+      if (in) it.out[i] = y;
+    } else {
+      const DF rr = walk_point<ArDF32, DMAX, false>(it.tree, x, lds);
+      if (in) {
+        double y;
+        float cond;
+        flag = df32_finish(rr, it.tol, 0, y, cond);
+        it.out[i] = y;
+        if (it.cond) it.cond[i] = cond;
+      }
+    }
+    append_flagged(flag, i, it.list, &counters[r]);
+  }
+}
+
+template <int DMAX>
+__global__ __launch_bounds__(kBlock) void k_serve_fallback(WorkTable* wt) {
+  extern __shared__ __align__(16) char lds[];
+  const int n = wt->n_items;
+  const WorkItem* items = table_items(wt);
+  const int64_t* counters = table_counters(wt);
+  for (int r = 0; r < n; ++r) {
+    const WorkItem& it = items[r];
+    if (it.domain != FPE_F32C) continue;
+    const int64_t cnt = counters[r];
+    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < cnt; base += (int64_t)gridDim.x * kBlock) {
+      const int64_t k = base + threadIdx.x;
+      const int64_t i = k < cnt ? it.list[k] : -1;
+      double x[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) x[j] = (i >= 0 && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
+      const DD rr = walk_point<ArDD, DMAX, false>(it.tree, x, lds);
+      if (i >= 0) it.out[i] = rr.h + rr.l;
+    }
+  }
+}
+
+ServeKernels serve_kernels() {
+  ServeKernels k;
+  k.zero = (const void*)k_serve_zero;
+  k.walk8 = (const void*)k_serve_walk<8>;
+  k.walk16 = (const void*)k_serve_walk<kMaxDepth>;
+  k.fallback8 = (const void*)k_serve_fallback<8>;
+  k.fallback16 = (const void*)k_serve_fallback<kMaxDepth>;
+  return k;
+}
+
+size_t work_table_bytes() {
+  return 256 + sizeof(WorkItem) * kMaxServe + sizeof(int64_t) * (2 * kMaxServe + 1);
+}
+
+}  // namespace fpe

@@ -1,0 +1,83 @@
+"""GPU composition p(q(x)) mod 2^31 - 1 through the evaluation tree, bit-exact
+against the oracle's schoolbook expansion; at full size every instance is
+checked by Schwartz-Zippel evaluation at random points and a sample of
+instances coefficient by coefficient."""
+import numpy as np
+import pytest
+import torch
+
+import fpe_inputs
+import paper_1307_5655_amd as fpe
+from oracle import compose as ocomp
+from oracle import native
+
+pytestmark = pytest.mark.gpu
+P31 = fpe.P31
+
+
+def say(msg):
+    print(msg, flush=True)
+
+
+def gpu_compose(P, Q, scheme, dev):
+    b, dp1 = P.shape
+    ex = np.arange(dp1, dtype=np.int32).reshape(-1, 1)
+    t = fpe.Tree(ex, P.astype(np.uint64), scheme, fpe.MODP, P31).upload(dev)
+    q = torch.from_numpy(np.ascontiguousarray(Q.astype(np.int32))).to(dev)
+    out = fpe.compose(t, q)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("scheme", ["horner", "estrin", "balanced"])
+def test_compose_small_batch_exact(dev, scheme):
+    say(f"compose 48 x (255 o 15) {scheme}")
+    inp = fpe_inputs.compose_batch(batch=48)
+    got = gpu_compose(inp.p, inp.q, scheme, dev)
+    want = native.compose_modp(inp.p, inp.q, P31)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("dp,dq", [(1, 1), (7, 3), (20, 1), (33, 5), (64, 2)])
+def test_compose_shapes_exact(dev, dp, dq):
+    say(f"compose shapes dp={dp} dq={dq}")
+    g = np.random.default_rng([dp, dq])
+    P = g.integers(0, P31, size=(5, dp + 1), dtype=np.uint32)
+    Q = g.integers(0, P31, size=(5, dq + 1), dtype=np.uint32)
+    for scheme in ["horner", "estrin", "balanced", "balanced_floor"]:
+        got = gpu_compose(P, Q, scheme, dev)
+        for b in range(5):
+            assert got[b].tolist() == ocomp.compose(P[b].tolist(), Q[b].tolist(), P31), (scheme, b)
+
+
+def test_compose_special_cases(dev):
+    say("compose special cases")
+    g = np.random.default_rng(5)
+    P = g.integers(0, P31, size=(3, 17), dtype=np.uint32)
+    # q = x gives p
+    Q = np.zeros((3, 2), dtype=np.uint32)
+    Q[:, 1] = 1
+    assert np.array_equal(gpu_compose(P, Q, "balanced", dev)[:, :17], P)
+    # sparse p (zero coefficients, zero constant term): p = x^k gives q^k
+    P2 = np.zeros((2, 9), dtype=np.uint32)
+    P2[:, 8] = 1
+    Q2 = g.integers(0, P31, size=(2, 4), dtype=np.uint32)
+    got = gpu_compose(P2, Q2, "estrin", dev)
+    for b in range(2):
+        for t in [3, 77, P31 - 5]:
+            assert ocomp.horner_at(got[b].tolist(), t, P31) == pow(ocomp.horner_at(Q2[b].tolist(), t, P31), 8, P31)
+
+
+def test_compose_full_size_schwartz_zippel(dev):
+    say("compose 4096 x (255 o 15) balanced + horner, Schwartz-Zippel on every instance")
+    inp = fpe_inputs.compose_batch()
+    for scheme in ["balanced", "horner"]:
+        got = gpu_compose(inp.p, inp.q, scheme, dev)
+        assert got.shape == (4096, 255 * 15 + 1)
+        rng = np.random.default_rng(17)
+        for b in range(4096):
+            t = int(rng.integers(2, P31 - 1))
+            assert ocomp.horner_at(got[b].tolist(), t, P31) == ocomp.compose_at(inp.p[b].tolist(), inp.q[b].tolist(), t, P31), (scheme, b)
+        idx = [0, 1, 2047, 4095]
+        want = native.compose_modp(inp.p[idx], inp.q[idx], P31)
+        assert np.array_equal(got[idx], want)
