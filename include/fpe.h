@@ -137,6 +137,7 @@ typedef struct {
   int32_t n_table;         /* powers held per point in the table (incl. chain temporaries) */
   int32_t n_chain;         /* steps of the power chain (Section 2.2, fast exponentiation) */
   int32_t n_offtable;      /* walk steps whose power is computed on the fly */
+  int32_t n_pair_ops;      /* walk steps whose power is the product of two table entries */
 } fpe_tree_info;
 
 fpe_status fpe_tree_get_info(const fpe_tree* t, fpe_tree_info* info);

@@ -48,7 +48,7 @@ class TreeInfo(ctypes.Structure):
                 ("max_slot", ctypes.c_int32), ("max_lazy_height", ctypes.c_int32),
                 ("walk_depth", ctypes.c_int32), ("n_powers", ctypes.c_int32),
                 ("n_table", ctypes.c_int32), ("n_chain", ctypes.c_int32),
-                ("n_offtable", ctypes.c_int32)]
+                ("n_offtable", ctypes.c_int32), ("n_pair_ops", ctypes.c_int32)]
 
 
 class EvalOpts(ctypes.Structure):

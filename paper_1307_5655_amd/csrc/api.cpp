@@ -17,10 +17,11 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 void layout(fpe_tree* t) {
   size_t off = 0;
+  // each op array is followed by one zero record (the walk reads one op ahead)
   t->off_ops64 = off;
-  off = align256(off + t->ops64.size() * sizeof(OpF64));
+  off = align256(off + (t->ops64.size() + 1) * sizeof(OpF64));
   t->off_ops32 = off;
-  off = align256(off + t->ops32.size() * sizeof(OpF32));
+  off = align256(off + (t->ops32.size() + 1) * sizeof(OpF32));
   t->off_chain = off;
   off = align256(off + std::max<size_t>(t->chain.size(), 1) * sizeof(ChainStep));
   t->off_coef = off;
@@ -93,6 +94,7 @@ fpe_status fpe_tree_get_info(const fpe_tree* t, fpe_tree_info* info) {
   info->n_table = t->n_table;
   info->n_chain = (int32_t)t->chain.size();
   info->n_offtable = t->n_offtable;
+  info->n_pair_ops = t->n_pairs;
   return FPE_OK;
 }
 
@@ -111,8 +113,16 @@ fpe_status fpe_tree_upload(fpe_tree* t, void* dev_buf, size_t bytes, void* strea
   if (((uintptr_t)dev_buf) & 255) return fail(FPE_EINVAL, "device buffer must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   char* b = (char*)dev_buf;
-  hipError_t e = hipSuccess;
-  if (!t->ops64.empty())
+  // the zero record after each op array (read ahead by the walk), copied from
+  // a zero block the tree owns so the call records no memset
+  static const OpF64 kZero64[1] = {};
+  static const OpF32 kZero32[1] = {};
+  hipError_t e = hipMemcpyAsync(b + t->off_ops64 + t->ops64.size() * sizeof(OpF64), kZero64, sizeof(OpF64),
+                                hipMemcpyHostToDevice, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(b + t->off_ops32 + t->ops32.size() * sizeof(OpF32), kZero32, sizeof(OpF32),
+                       hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !t->ops64.empty())
     e = hipMemcpyAsync(b + t->off_ops64, t->ops64.data(), t->ops64.size() * sizeof(OpF64),
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !t->ops32.empty())
@@ -187,7 +197,7 @@ void write_tree(const fpe_tree* t, Writer& w) {
   w.pod(kMagic);
   w.pod(t->nvars); w.pod(t->domain); w.pod(t->modulus); w.pod(t->batch); w.pod(t->n_terms);
   w.pod(t->n_table); w.pod(t->n_powers); w.pod(t->depth); w.pod(t->max_slot); w.pod(t->max_lh);
-  w.pod(t->n_offtable);
+  w.pod(t->n_offtable); w.pod(t->n_pairs);
   w.vec(t->nodes); w.vec(t->exps); w.vec(t->coef_rows); w.vec(t->ops64); w.vec(t->ops32);
   w.vec(t->chain); w.vec(t->table_var); w.vec(t->table_deg);
 }
@@ -221,7 +231,7 @@ fpe_status fpe_tree_deserialize(const void* buf, size_t bytes, fpe_tree** out) {
   auto* t = new fpe_tree();
   r.pod(t->nvars); r.pod(t->domain); r.pod(t->modulus); r.pod(t->batch); r.pod(t->n_terms);
   r.pod(t->n_table); r.pod(t->n_powers); r.pod(t->depth); r.pod(t->max_slot); r.pod(t->max_lh);
-  r.pod(t->n_offtable);
+  r.pod(t->n_offtable); r.pod(t->n_pairs);
   r.vec(t->nodes); r.vec(t->exps); r.vec(t->coef_rows); r.vec(t->ops64); r.vec(t->ops32);
   r.vec(t->chain); r.vec(t->table_var); r.vec(t->table_deg);
   if (!r.ok || r.o != bytes || t->nvars < 1 || t->nvars > 8 ||
@@ -252,8 +262,11 @@ fpe_status fpe_tree_deserialize(const void* buf, size_t bytes, fpe_tree** out) {
   }
   for (const auto& o : t->ops64) {
     uint32_t p = op_pidx(o.info);
+    const uint32_t p2 = op_pidx2(o.info);
     if (op_kind(o.info) > kEnd || (p != kOffTable && p >= (uint32_t)t->n_table) ||
-        op_var(o.info) >= (uint32_t)t->nvars) {
+        (p2 != kNoPair && (p2 >= (uint32_t)t->n_table || p == kOffTable)) ||
+        (p2 != kNoPair && (op_deg(o.deg) & kThirdBit) && (op_deg(o.deg) & 0xFFu) >= (uint32_t)t->n_table) ||
+        op_var(o.info) >= (uint32_t)t->nvars || (int)op_level(o.info) > kMaxDepth) {
       delete t;
       return fail(FPE_EINVAL, "corrupt serialised tree (program)");
     }

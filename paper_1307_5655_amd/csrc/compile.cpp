@@ -18,10 +18,12 @@
 // B(n) = ceil(n/2) on the degree; a nested block whose coefficient polynomial
 // has no constant term gets a junction node with coefficient 0.
 #include <algorithm>
+#include <array>
 #include <cmath>
 #include <cstring>
 #include <map>
 #include <numeric>
+#include <set>
 #include <unordered_map>
 
 #include "fpe_internal.h"
@@ -201,6 +203,123 @@ struct PowerPlan {
     if (d == 1) chain.push_back({(uint8_t)kChainLoad, (uint8_t)id, (uint8_t)var, 0});
     else chain.push_back({(uint8_t)kChainMul, (uint8_t)id, (uint8_t)a, (uint8_t)b});
     return id;
+  }
+};
+
+// Pointwise walks: choose at most `cap` table powers greedily so that as many
+// walk steps as possible read their power either from the table or as the
+// product of two table entries.  An entry is added only when the chain can
+// compute it (x itself, or the product of two entries already chosen); each
+// round adds the computable power that newly covers the most steps, or, when
+// none covers anything new, the next missing intermediate (halving chain) of
+// the most used uncovered power.
+struct CoverPlan {
+  std::vector<std::pair<int32_t, int32_t>> entries;   // in chain order
+  std::vector<ChainStep> chain;
+  std::map<std::pair<int32_t, int32_t>, int32_t> index;
+
+  bool has(int32_t v, int32_t d) const { return index.count({v, d}) != 0; }
+  // a pair (a, b) of entries with a + b = d, or (-1, -1)
+  std::pair<int32_t, int32_t> split(int32_t v, int32_t d) const {
+    for (auto& e : entries) {
+      if (e.first != v || e.second >= d) continue;
+      auto it = index.find({v, d - e.second});
+      if (it != index.end()) return {index.at(e), it->second};
+    }
+    return {-1, -1};
+  }
+  bool computable(int32_t v, int32_t d) const { return d == 1 || split(v, d).first >= 0; }
+  // a triple (a, b, c) of entries with a + b + c = d, or a = -1
+  std::array<int32_t, 3> split3(int32_t v, int32_t d) const {
+    for (auto& e : entries) {
+      if (e.first != v || e.second >= d) continue;
+      auto ab = split(v, d - e.second);
+      if (ab.first >= 0) return {index.at(e), ab.first, ab.second};
+    }
+    return {-1, -1, -1};
+  }
+  bool covered(int32_t v, int32_t d) const {
+    return has(v, d) || split(v, d).first >= 0 || split3(v, d)[0] >= 0;
+  }
+  void add(int32_t v, int32_t d) {
+    int32_t id = (int32_t)entries.size();
+    if (d == 1) {
+      chain.push_back({(uint8_t)kChainLoad, (uint8_t)id, (uint8_t)v, 0});
+    } else {
+      auto ab = split(v, d);
+      chain.push_back({(uint8_t)kChainMul, (uint8_t)id, (uint8_t)ab.first, (uint8_t)ab.second});
+    }
+    entries.push_back({v, d});
+    index[{v, d}] = id;
+  }
+
+  void build(const std::map<std::pair<int32_t, int32_t>, int64_t>& freq, int32_t cap) {
+    // candidates: used powers and their halving intermediates
+    std::set<std::pair<int32_t, int32_t>> cand;
+    for (auto& kv : freq) {
+      std::vector<int32_t> st{kv.first.second};
+      while (!st.empty()) {
+        int32_t d = st.back();
+        st.pop_back();
+        if (!cand.insert({kv.first.first, d}).second || d == 1) continue;
+        st.push_back(d / 2);
+        st.push_back(d - d / 2);
+      }
+    }
+    while ((int32_t)entries.size() < cap) {
+      // uncovered steps
+      std::vector<std::pair<std::pair<int32_t, int32_t>, int64_t>> un;
+      for (auto& kv : freq)
+        if (!covered(kv.first.first, kv.first.second)) un.push_back(kv);
+      if (un.empty()) break;
+      std::pair<int32_t, int32_t> best{-1, -1};
+      int64_t bestgain = 0;
+      for (auto& c : cand) {
+        if (has(c.first, c.second) || !computable(c.first, c.second)) continue;
+        int64_t gain = 0;
+        for (auto& u : un) {
+          if (u.first.first != c.first) continue;
+          const int32_t d = u.first.second;
+          if (d == c.second || (d > c.second && (has(c.first, d - c.second) || d - c.second == c.second)))
+            gain += u.second;
+        }
+        if (gain > bestgain || (gain == bestgain && gain > 0 && c.second < best.second)) {
+          bestgain = gain;
+          best = c;
+        }
+      }
+      if (bestgain == 0) {
+        // build towards the most used uncovered power along its halving chain
+        auto top = *std::max_element(un.begin(), un.end(),
+                                     [](auto& a, auto& b) { return a.second < b.second; });
+        const int32_t v = top.first.first;
+        int32_t d = top.first.second;
+        // descend to the first computable missing intermediate
+        for (;;) {
+          if (!has(v, d) && computable(v, d)) break;
+          int32_t h = d - d / 2;   // the larger half
+          if (!has(v, h)) d = h;
+          else if (!has(v, d / 2)) d = d / 2;
+          else break;
+        }
+        if (has(v, d) || !computable(v, d)) break;
+        best = {v, d};
+      }
+      add(best.first, best.second);
+    }
+    // room left: turn the most used products into direct entries
+    while ((int32_t)entries.size() < cap) {
+      std::pair<int32_t, int32_t> best{-1, -1};
+      int64_t bf = 0;
+      for (auto& kv : freq)
+        if (!has(kv.first.first, kv.first.second) && computable(kv.first.first, kv.first.second) &&
+            kv.second > bf) {
+          bf = kv.second;
+          best = kv.first;
+        }
+      if (bf == 0) break;
+      add(best.first, best.second);
+    }
   }
 };
 
@@ -403,20 +522,52 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
   std::vector<std::pair<int64_t, std::pair<int32_t, int32_t>>> byf;
   for (auto& kv : freq) byf.push_back({kv.second, kv.first});
   std::stable_sort(byf.begin(), byf.end(), [](auto& a, auto& b) { return a.first > b.first; });
-  // largest prefix of the most used powers whose chain fits the table
+  // The table holds the most used powers and the chain temporaries they
+  // need, within a cap (16 entries for the pointwise walks, so the per-point
+  // table stays small in LDS); a power left out is read as the product of two
+  // entries when its degree is the sum of two table degrees, else computed
+  // on the fly.  A batch tree (composition) keeps its coefficients per
+  // instance, so its ops carry node indices instead of coefficient values,
+  // and its table may hold up to 48 entries without products.
+  const bool index_ops = domain == FPE_MODP && modulus == kP31;
+  const int32_t cap = index_ops ? kMaxTable : kTableCap;
   PowerPlan plan;
-  size_t take = byf.size();
-  for (;;) {
-    plan = PowerPlan();
-    for (size_t k = 0; k < take && plan.ok; ++k)
-      plan.ensure(byf[k].second.first, byf[k].second.second, kMaxTable);
-    if (plan.ok) break;
-    --take;
+  if (index_ops) {
+    for (size_t k = 0; k < byf.size(); ++k) {
+      PowerPlan tmp = plan;
+      tmp.ensure(byf[k].second.first, byf[k].second.second, cap);
+      if (tmp.ok) plan = std::move(tmp);
+    }
+  } else {
+    // 16 entries keep the per-point table small; a tree whose powers cannot
+    // all be covered (directly or as products) within 16 gets 24, 32 or 48
+    std::map<std::pair<int32_t, int32_t>, int64_t> fr(freq.begin(), freq.end());
+    // A few walk steps may compute their power on the fly instead (at most
+    // 1 in 256 steps) rather than double the table.
+    int64_t nsteps = 0;
+    for (auto& kv : fr) nsteps += kv.second;
+    for (int32_t c : {16, 24, 32, kMaxTable}) {
+      CoverPlan cp;
+      cp.build(fr, c);
+      int64_t missing = 0;
+      for (auto& kv : fr)
+        if (!cp.covered(kv.first.first, kv.first.second)) missing += kv.second;
+      plan.entries = cp.entries;
+      plan.chain = cp.chain;
+      plan.index = cp.index;
+      if (missing == 0 || (c == 16 && missing * 256 <= nsteps)) break;
+    }
   }
+  std::vector<std::pair<int32_t, int32_t>> pending;
+  for (auto& kv : freq)
+    if (!plan.index.count(kv.first)) pending.push_back(kv.first);
   // renumber: used entries by frequency first, chain temporaries after
   std::vector<int32_t> rank(plan.entries.size(), -1);
   int32_t nr = 0;
-  for (size_t k = 0; k < take; ++k) rank[plan.index[byf[k].second]] = nr++;
+  for (size_t k = 0; k < byf.size(); ++k) {
+    auto it = plan.index.find(byf[k].second);
+    if (it != plan.index.end() && rank[it->second] < 0) rank[it->second] = nr++;
+  }
   for (size_t id = 0; id < plan.entries.size(); ++id)
     if (rank[id] < 0) rank[id] = nr++;
   t->n_table = (int32_t)plan.entries.size();
@@ -435,15 +586,52 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
     }
     t->chain.push_back(c);
   }
-  auto pidx_of = [&](const fpe_node& nd) -> uint32_t {
+  // pending powers: the product of two (or three) table entries of the same
+  // variable
+  std::map<std::pair<int32_t, int32_t>, std::array<uint32_t, 3>> pairs;
+  if (!index_ops) {
+    auto find = [&](int32_t v, int32_t d) -> int32_t {
+      auto it = plan.index.find({v, d});
+      return it == plan.index.end() ? -1 : rank[it->second];
+    };
+    for (auto& pw : pending) {
+      bool done = false;
+      for (int32_t e = 0; e < t->n_table && !done; ++e) {
+        if (t->table_var[e] != pw.first || t->table_deg[e] >= pw.second) continue;
+        const int32_t f = find(pw.first, pw.second - t->table_deg[e]);
+        if (f >= 0) {
+          pairs[pw] = {(uint32_t)e, (uint32_t)f, kNoPair};
+          done = true;
+        }
+      }
+      for (int32_t e = 0; e < t->n_table && !done; ++e) {
+        if (t->table_var[e] != pw.first || t->table_deg[e] >= pw.second) continue;
+        for (int32_t g = 0; g < t->n_table && !done; ++g) {
+          if (t->table_var[g] != pw.first || t->table_deg[e] + t->table_deg[g] >= pw.second) continue;
+          const int32_t f = find(pw.first, pw.second - t->table_deg[e] - t->table_deg[g]);
+          if (f >= 0) {
+            pairs[pw] = {(uint32_t)e, (uint32_t)g, (uint32_t)f};
+            done = true;
+          }
+        }
+      }
+    }
+  }
+  auto pidx_of = [&](const fpe_node& nd, uint32_t& p2, uint32_t& p3) -> uint32_t {
+    p2 = kNoPair;
+    p3 = kNoPair;
     auto it = plan.index.find({nd.var, nd.pdeg});
-    return it == plan.index.end() ? kOffTable : (uint32_t)rank[it->second];
+    if (it != plan.index.end()) return (uint32_t)rank[it->second];
+    auto jt = pairs.find({nd.var, nd.pdeg});
+    if (jt != pairs.end()) {
+      p2 = jt->second[1];
+      p3 = jt->second[2];
+      return jt->second[0];
+    }
+    return kOffTable;
   };
 
   // ---- walk program (stack form of the walk of Section 2.1)
-  // A batch tree (composition) keeps its coefficients per instance, so its
-  // ops carry node indices instead of coefficient values.
-  const bool index_ops = domain == FPE_MODP && modulus == kP31;
   auto bits = [&](int64_t i) -> uint64_t {
     if (index_ops) return (uint64_t)i;
     if (domain == FPE_MODP) return t->coef_rows[i];
@@ -456,10 +644,15 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
   for (int64_t i = 0; i < N; ++i) {
     const fpe_node& nd = t->nodes[i];
     OpF64 op{};
-    uint32_t pidx = nd.pdeg > 0 ? pidx_of(nd) : kOffTable;
+    const int32_t depth_before = depth;
+    uint32_t pidx2 = kNoPair, pidx3 = kNoPair;
+    uint32_t pidx = nd.pdeg > 0 ? pidx_of(nd, pidx2, pidx3) : kOffTable;
     if (nd.pdeg > 0 && pidx == kOffTable) t->n_offtable++;
-    uint32_t info = (pidx << 8) | ((uint32_t)nd.var << 16) | ((uint32_t)std::min(depth, 31) << 20);
-    op.deg = (uint32_t)nd.pdeg;
+    if (pidx2 != kNoPair) t->n_pairs++;
+    uint32_t info = (pidx << 8) | ((uint32_t)nd.var << 16) | ((uint32_t)std::min(depth, 31) << 20) |
+                    (pidx2 << 25);
+    // deg: the partial degree (used on the fly), or a third table index
+    op.deg = pidx3 != kNoPair ? (kThirdBit | pidx3) : (uint32_t)nd.pdeg;
     if (par[i] < 0) {
       info |= kEnd | kBitEnd;
       if (ch[i].empty()) {
@@ -492,6 +685,17 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
       maxd = std::max(maxd, depth);
     }
     op.info = info;
+    {
+      // dispatch code: depth, kind, power class (END: depth 0, kind 0)
+      uint32_t pc = kPowOther;
+      if (pidx2 == kNoPair && pidx < (uint32_t)kRegPowers) pc = pidx;
+      else if (pidx2 == kNoPair && pidx != kOffTable) pc = kPowLds;
+      const uint32_t kind = op_kind(info);
+      const uint32_t lvl = (uint32_t)std::min(depth_before, 15);
+      const uint32_t code = kind == kEnd ? make_code(0, 0, (info & kEndHasPow) ? pc : kPowOther)
+                                         : make_code(lvl, kind, pc);
+      op.deg = (op.deg & 0xFFFFFu) | (code << 20);
+    }
     t->ops64.push_back(op);
   }
   t->depth = std::max(maxd, 1);

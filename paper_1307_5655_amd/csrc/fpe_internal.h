@@ -34,9 +34,12 @@ enum OpKind : uint32_t { kLeafAdd = 0, kNodeOpen = 1, kLeafOpen = 2, kNodeAdd = 
 // a power (END), bits 5-7 the kind as flags (leaf / first child / end) for a
 // two-test dispatch, bits 8-15 power-table index (kOffTable = on the fly),
 // bits 16-19 variable, bits 20-24 the stack depth L before the op (so a flat
-// loop can address the accumulators with compile-time indices).  deg holds
-// the partial degree (for on-the-fly powers).
+// loop can address the accumulators with compile-time indices), bits 25-31 a
+// second table index (kNoPair if none): the power is then the product of the
+// two entries.  deg holds the partial degree (for on-the-fly powers).
 constexpr uint32_t kOffTable = 255;
+constexpr uint32_t kNoPair = 127;
+constexpr uint32_t kThirdBit = 1u << 19;   // in deg: the power has a third factor (index in bits 0-7)
 constexpr uint32_t kEndLeafRoot = 1u << 3;
 constexpr uint32_t kEndHasPow = 1u << 4;
 constexpr uint32_t kBitLeaf = 1u << 5;
@@ -47,6 +50,21 @@ __host__ __device__ inline uint32_t op_kind(uint32_t info) { return info & 7u; }
 __host__ __device__ inline uint32_t op_pidx(uint32_t info) { return (info >> 8) & 255u; }
 __host__ __device__ inline uint32_t op_var(uint32_t info) { return (info >> 16) & 15u; }
 __host__ __device__ inline uint32_t op_level(uint32_t info) { return (info >> 20) & 31u; }
+__host__ __device__ inline uint32_t op_pidx2(uint32_t info) { return (info >> 25) & 127u; }
+
+// The dispatch code of an op, in the top 12 bits of its deg field (the
+// partial degree itself, < 2^20, uses the low 20 bits): bits 0-3 the stack
+// depth L, bits 4-5 the kind (LEAF_ADD, NODE_OPEN, LEAF_OPEN, NODE_ADD),
+// bits 6-8 where its power comes from (0-3: register entry 0-3, 4: one LDS
+// entry, 5: a product of two entries or computed on the fly).  LEAF_ADD at
+// depth 0 cannot occur, so codes with L = 0 and kind 0 mark the root (END).
+constexpr int kRegPowers = 4;   // table entries kept in registers
+enum PowClass : uint32_t { kPowLds = 4, kPowOther = 5 };
+constexpr uint32_t make_code(uint32_t level, uint32_t kind, uint32_t pclass) {
+  return (level & 15u) | (kind << 4) | (pclass << 6);
+}
+__host__ __device__ inline uint32_t op_code(uint32_t deg) { return deg >> 20; }
+__host__ __device__ inline uint32_t op_deg(uint32_t deg) { return deg & 0xFFFFFu; }
 
 struct alignas(32) OpF64 {   // FP64 / double-double / mod-p walks
   uint64_t a;                // c(N) or c(P): FP64 bits or residue
@@ -139,6 +157,7 @@ struct fpe_tree {
   int32_t max_slot = 0;
   int32_t max_lh = 0;
   int32_t n_offtable = 0;
+  int32_t n_pairs = 0;
   // device image
   void* dev = nullptr;
   size_t off_ops64 = 0, off_ops32 = 0, off_chain = 0, off_coef = 0, dev_bytes = 0;
@@ -155,8 +174,9 @@ size_t eval_workspace_bytes(const fpe_tree* t, int64_t npts);
 fpe_status launch_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out,
                           void* ws, size_t ws_bytes, void* stream);
 size_t compose_workspace_bytes(const fpe_tree* t, int32_t dq);
-constexpr int kMaxDepth = 16;   // stack depth the kernels hold
-constexpr int kMaxTable = 48;   // power-table entries held per point
+constexpr int kMaxDepth = 16;   // stack depth the kernels hold (4 bits of the code)
+constexpr int kMaxTable = 48;   // power-table entries held per point (composition)
+constexpr int kTableCap = 16;   // power-table entries per point for the pointwise walks
 constexpr int kMaxServe = 256;  // requests per fused launch
 constexpr int kServeGrid = 4096;   // fixed grid of the fused kernels (workgroups)
 // Fused served launch (walk.hip).
@@ -174,7 +194,8 @@ __host__ __device__ inline int64_t* table_prefix(WorkTable* t) {
   return (int64_t*)(table_items(t) + kMaxServe);
 }
 __host__ __device__ inline int64_t* table_counters(WorkTable* t) { return table_prefix(t) + kMaxServe + 1; }
-size_t lds_bytes(const fpe_tree* t, int domain);
+constexpr int kLdsFallback = 3;
+size_t lds_bytes(const fpe_tree* t, int kind);
 
 // One pointwise launch (walk.hip picks the shape; the eval_*.hip files hold
 // the kernels).

@@ -1,6 +1,7 @@
 // Fused served launches: one work table of requests (different trees, point
 // counts and forms) in one launch over a fixed grid that strides over the
-// 64-point blocks of all requests.
+// 64-point blocks of all requests.  Served trees may hold powers outside the
+// table (computed on the fly), so these kernels take that path too.
 #include "walk_core.h"
 
 namespace fpe {
@@ -38,10 +39,10 @@ __global__ __launch_bounds__(kBlock) void k_serve_walk(WorkTable* wt) {
     for (int j = 0; j < 8; ++j) x[j] = (in && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
     bool flag = false;
     if (it.domain == FPE_F64) {
-      const double y = walk_point<ArF64, DMAX, false>(it.tree, x, lds);
+      const double y = walk_point<ArF64, DMAX, true>(it.tree, x, lds);
       if (in) it.out[i] = y;
     } else {
-      const DF rr = walk_point<ArDF32, DMAX, false>(it.tree, x, lds);
+      const DF rr = walk_point<ArDF32, DMAX, true>(it.tree, x, lds);
       if (in) {
         double y;
         float cond;
@@ -70,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_fallback(WorkTable* wt) {
       double x[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) x[j] = (i >= 0 && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
-      const DD rr = walk_point<ArDD, DMAX, false>(it.tree, x, lds);
+      const DD rr = walk_point<ArDD, DMAX, true>(it.tree, x, lds);
       if (i >= 0) it.out[i] = rr.h + rr.l;
     }
   }

@@ -231,7 +231,7 @@ bool try_launch(fpe_server* s, Slot& sl) {
     it.domain = q.r.domain;
     table_prefix(sl.host[c])[n[c]] = blocks[c];
     blocks[c] += (q.r.npts + 63) / 64;
-    lds[c] = std::max(lds[c], lds_bytes(q.r.tree, q.r.domain));
+    lds[c] = std::max(lds[c], lds_bytes(q.r.tree, kLdsFallback));
     sl.tickets[c].push_back(q.ticket);
     n[c]++;
   }

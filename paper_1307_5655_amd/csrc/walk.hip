@@ -7,11 +7,16 @@ namespace fpe {
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
-size_t lds_bytes(const fpe_tree* t, int domain) {
-  size_t per = domain == FPE_MODP ? TabM61::bytes_per_entry
-             : domain == FPE_F32C ? std::max(TabP3::bytes_per_entry, TabF64::bytes_per_entry)
-                                  : TabF64::bytes_per_entry;
-  return std::max<size_t>(16, per * (size_t)t->n_table);
+// LDS of one wavefront's power table (one point per lane) for a kernel kind:
+// FPE_F64, FPE_F32C (three-float powers), FPE_MODP, or kLdsFallback (the
+// double-double re-evaluation; also the size every served kernel reserves).
+size_t lds_bytes(const fpe_tree* t, int kind) {
+  size_t per = kind == FPE_MODP ? TabM61::bytes_per_entry
+             : kind == FPE_F32C ? TabP3::bytes_per_entry
+             : kind == kLdsFallback ? std::max(TabDD::bytes_per_entry, TabP3::bytes_per_entry)
+             : t->n_table > kTableCap ? TabF64::bytes_per_entry_big
+                                    : TabF64::bytes_per_entry;
+  return std::max<size_t>(16, per * (size_t)lds_entries(t->n_table));
 }
 
 size_t eval_workspace_bytes(const fpe_tree* t, int64_t npts) {
@@ -82,7 +87,7 @@ fpe_status launch_eval(const fpe_tree* t, const void* const* pts, int64_t npts, 
     KernelLaunch F = L;
     F.ppl = 1;
     F.nblocks = std::min<int64_t>(blocks_for(npts, 1), 4096);
-    F.lds = lds_bytes(t, FPE_F64);
+    F.lds = lds_bytes(t, kLdsFallback);
     launch_fallback(F, o.list, o.count, (double*)out);
     if (opts->nfallback_out) {
       hipError_t e = hipMemcpyAsync(opts->nfallback_out, o.count, sizeof(int64_t),

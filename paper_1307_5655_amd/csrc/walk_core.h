@@ -20,6 +20,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "fpe_internal.h"
 
@@ -94,6 +95,21 @@ __device__ __forceinline__ uint64_t pow_m61(uint64_t x, uint32_t d) {
   return r;
 }
 
+// Coordinate v of a point (v is wave-uniform; a switch keeps x in registers).
+template <class T>
+__device__ __forceinline__ T coord(const T* x, uint32_t v) {
+  switch (v) {
+    case 0: return x[0];
+    case 1: return x[1];
+    case 2: return x[2];
+    case 3: return x[3];
+    case 4: return x[4];
+    case 5: return x[5];
+    case 6: return x[6];
+    default: return x[7];
+  }
+}
+
 // ----------------------------------------------------------------------------
 // arithmetic policies
 // ----------------------------------------------------------------------------
@@ -118,9 +134,8 @@ struct ArF64 {
   }
   static __device__ __forceinline__ Acc leaf_root(const Op& o) { return u2d(o.a); }
   static __device__ __forceinline__ Acc mul(Acc a, Pow X) { return a * X; }
-  static __device__ __forceinline__ Pow off_table(const In* x, const Op& o) {
-    return pow_f64(x[op_var(o.info)], o.deg);
-  }
+  static __device__ __forceinline__ Pow off_table(In xv, const Op& o) { return pow_f64(xv, op_deg(o.deg)); }
+  static __device__ __forceinline__ Pow pair(Pow a, Pow b) { return a * b; }
 };
 
 struct ArDD {   // double-double walk (fallback), double-double powers
@@ -143,15 +158,16 @@ struct ArDD {   // double-double walk (fallback), double-double powers
   }
   static __device__ __forceinline__ Acc leaf_root(const Op& o) { return DD{u2d(o.a), 0.0}; }
   static __device__ __forceinline__ Acc mul(const Acc& a, const Pow& X) { return dd_mul(a, X); }
-  static __device__ __forceinline__ Pow off_table(const In* x, const Op& o) {
+  static __device__ __forceinline__ Pow off_table(In xv, const Op& o) {
     // binary exponentiation in double-double
-    DD r{1.0, 0.0}, b{x[op_var(o.info)], 0.0};
-    for (uint32_t d = o.deg; d; d >>= 1) {
+    DD r{1.0, 0.0}, b{xv, 0.0};
+    for (uint32_t d = op_deg(o.deg); d; d >>= 1) {
       if (d & 1u) r = dd_mul(r, b);
       b = dd_mul(b, b);
     }
     return r;
   }
+  static __device__ __forceinline__ Pow pair(const Pow& a, const Pow& b) { return dd_mul(a, b); }
 };
 
 struct ArM61 {
@@ -174,9 +190,8 @@ struct ArM61 {
   }
   static __device__ __forceinline__ Acc leaf_root(const Op& o) { return o.a; }
   static __device__ __forceinline__ Acc mul(Acc a, Pow X) { return m61_mul(a, X); }
-  static __device__ __forceinline__ Pow off_table(const In* x, const Op& o) {
-    return pow_m61(x[op_var(o.info)], o.deg);
-  }
+  static __device__ __forceinline__ Pow off_table(In xv, const Op& o) { return pow_m61(xv, op_deg(o.deg)); }
+  static __device__ __forceinline__ Pow pair(Pow a, Pow b) { return m61_mul(a, b); }
 };
 
 // Compensated FP32.  A value is hi + lo (double-float); alongside it the
@@ -249,9 +264,25 @@ struct ArDF32 {
   static __device__ __forceinline__ Acc mul(const Acc& a, const Pow& X) {
     return df_step(a.h, a.l, a.e, a.t, X, 0.f, 0.f, 0.f, 0.f);
   }
-  static __device__ __forceinline__ Pow off_table(const In* x, const Op& o) {
-    double v = pow_f64(x[op_var(o.info)], o.deg);
-    return split3(v);
+  static __device__ __forceinline__ Pow off_table(In xv, const Op& o) {
+    // binary exponentiation in double-double, split into three floats
+    DD r{1.0, 0.0}, b{xv, 0.0};
+    for (uint32_t d = op_deg(o.deg); d; d >>= 1) {
+      if (d & 1u) r = dd_mul(r, b);
+      b = dd_mul(b, b);
+    }
+    const float h = (float)r.h;
+    const double dd = (r.h - (double)h) + r.l;
+    const float m = (float)dd;
+    return P3{h, m, (float)(dd - (double)m)};
+  }
+  // the product of two table powers, in double-double, split again
+  static __device__ __forceinline__ Pow pair(const Pow& a, const Pow& b) {
+    const DD r = dd_mul(DD{(double)a.h + (double)a.m, (double)a.l}, DD{(double)b.h + (double)b.m, (double)b.l});
+    const float h = (float)r.h;
+    const double d = (r.h - (double)h) + r.l;
+    const float m = (float)d;
+    return P3{h, m, (float)(d - (double)m)};
   }
   static __device__ __forceinline__ P3 split3(double v) {
     float h = (float)v;
@@ -276,81 +307,208 @@ struct ArDF32 {
 
 constexpr int kWave = 64;
 
+__device__ __forceinline__ float rel_lo(const DD& r) {
+  return (r.h != 0.0 && isfinite(r.h)) ? (float)(r.l / r.h) : 0.f;
+}
+
+// The power chain of one point in double-double, in registers (at most
+// kTableCap entries; the low word kept relative to the high word as a float:
+// about 77 bits).  emit(i, value) receives every entry; regs(h, l) receives
+// the register arrays (entries 0..kRegPowers-1 read with static indices).
+template <class Emit, class Regs>
+__device__ __forceinline__ void chain_dd(const DevTree& tr, const double* x, Emit&& emit, Regs&& regs) {
+  double h[kTableCap];
+  float l[kTableCap];
+#pragma unroll
+  for (int i = 0; i < kTableCap; ++i) {
+    h[i] = 0.0;
+    l[i] = 0.f;
+  }
+  for (int c = 0; c < tr.n_chain; ++c) {
+    const ChainStep st = tr.chain[c];
+    double hh;
+    float ll;
+    if (st.kind == kChainLoad) {
+      hh = coord(x, st.s1);
+      ll = 0.f;
+    } else {
+      const double h1 = h[st.s1], h2 = h[st.s2];
+      const DD r = dd_mul(DD{h1, h1 * (double)l[st.s1]}, DD{h2, h2 * (double)l[st.s2]});
+      hh = r.h;
+      ll = rel_lo(r);
+    }
+    h[st.dst] = hh;
+    l[st.dst] = ll;
+  }
+  for (int i = kRegPowers; i < tr.n_table; ++i) emit(i, DD{h[i], h[i] * (double)l[i]});
+  if constexpr (std::is_invocable_v<Regs, const double*, const float*>) regs(h, l);
+  else regs(h);
+}
+
+// LDS entries of a table: small tables (at most kTableCap entries) keep
+// entries 0..kRegPowers-1 only in registers and the rest in LDS; larger
+// tables run their chain in LDS and keep every entry there.
+__device__ __forceinline__ int lds_first(int n_table) { return n_table <= kTableCap ? kRegPowers : 0; }
+__host__ __device__ inline int lds_entries(int n_table) {
+  return n_table <= kTableCap ? (n_table > kRegPowers ? n_table - kRegPowers : 0) : n_table;
+}
+
+// Register copies of entries 0..3 (static indices) and the dynamic reader.
+template <class E>
+struct RegPow {
+  E r[kRegPowers];
+  template <class Get>
+  __device__ __forceinline__ E any(uint32_t i, Get&& lds) const {
+    switch (i) {
+      case 0: return r[0];
+      case 1: return r[1];
+      case 2: return r[2];
+      case 3: return r[3];
+      default: return lds(i);
+    }
+  }
+};
+
 struct TabF64 {
-  double* hi;          // [n_table][stride]
-  float* lo;           // [n_table][stride], low word / high word
-  int col, stride;
-  double r0, r1;
+  double* hi;          // LDS entries [lds_first..n_table) at [(i - first) * stride + col]
+  float* lo;           // only for tables above kTableCap entries (chain in LDS)
+  int col, stride, first;
+  RegPow<double> rp;
+  static constexpr size_t bytes_per_entry = kWave * sizeof(double);
+  static constexpr size_t bytes_per_entry_big = kWave * (sizeof(double) + sizeof(float));
+  __device__ __forceinline__ void bind(char* lds, int n_table, int j, int ppl) {
+    stride = ppl * kWave;
+    col = j * kWave + (threadIdx.x & (kWave - 1));
+    first = lds_first(n_table);
+    hi = (double*)lds;
+    lo = (float*)(lds + (size_t)lds_entries(n_table) * stride * sizeof(double));
+  }
+  __device__ __forceinline__ double& at(uint32_t i) const { return hi[(i - first) * stride + col]; }
+  __device__ __forceinline__ void build(const DevTree& tr, const double* x) {
+#pragma unroll
+    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = 0.0;
+    if (tr.n_table <= kTableCap) {
+      chain_dd(tr, x, [&](int i, const DD& v) {
+        if (i >= kRegPowers) at(i) = v.h;
+      }, [&](const double* h) {
+#pragma unroll
+        for (int k = 0; k < kRegPowers; ++k) rp.r[k] = h[k];
+      });
+    } else {
+      for (int c = 0; c < tr.n_chain; ++c) {
+        const ChainStep st = tr.chain[c];
+        DD r;
+        if (st.kind == kChainLoad) {
+          r = DD{coord(x, st.s1), 0.0};
+        } else {
+          const double h1 = at(st.s1), h2 = at(st.s2);
+          r = dd_mul(DD{h1, h1 * (double)lo[st.s1 * stride + col]}, DD{h2, h2 * (double)lo[st.s2 * stride + col]});
+        }
+        at(st.dst) = r.h;
+        lo[st.dst * stride + col] = rel_lo(r);
+      }
+#pragma unroll
+      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? at(k) : 0.0;
+    }
+  }
+  template <int I>
+  __device__ __forceinline__ double reg() const { return rp.r[I]; }
+  __device__ __forceinline__ double get(uint32_t i) const { return at(i); }
+  __device__ __forceinline__ double getany(uint32_t i) const {
+    return rp.any(i, [&](uint32_t k) { return at(k); });
+  }
+};
+
+// The fallback reads the powers as double-double (hi + lo).
+struct TabDD {
+  double* hi;          // LDS entries, as TabF64
+  float* lo;           // low word / high word
+  int col, stride, first;
+  RegPow<DD> rp;
   static constexpr size_t bytes_per_entry = kWave * (sizeof(double) + sizeof(float));
   __device__ __forceinline__ void bind(char* lds, int n_table, int j, int ppl) {
     stride = ppl * kWave;
     col = j * kWave + (threadIdx.x & (kWave - 1));
+    first = lds_first(n_table);
     hi = (double*)lds;
-    lo = (float*)(lds + (size_t)n_table * stride * sizeof(double));
+    lo = (float*)(lds + (size_t)lds_entries(n_table) * stride * sizeof(double));
   }
-  __device__ __forceinline__ DD dd_at(uint32_t i) const {
-    const double h = hi[i * stride + col];
-    return DD{h, h * (double)lo[i * stride + col]};
+  __device__ __forceinline__ DD at(uint32_t i) const {
+    const double h = hi[(i - first) * stride + col];
+    return DD{h, h * (double)lo[(i - first) * stride + col]};
+  }
+  __device__ __forceinline__ void put(uint32_t i, const DD& v) const {
+    hi[(i - first) * stride + col] = v.h;
+    lo[(i - first) * stride + col] = rel_lo(v);
   }
   __device__ __forceinline__ void build(const DevTree& tr, const double* x) {
-    for (int c = 0; c < tr.n_chain; ++c) {
-      const ChainStep st = tr.chain[c];
-      double h;
-      float l;
-      if (st.kind == kChainLoad) {
-        h = x[st.s1];
-        l = 0.f;
-      } else {
-        DD r = dd_mul(dd_at(st.s1), dd_at(st.s2));
-        h = r.h;
-        l = (r.h != 0.0 && isfinite(r.h)) ? (float)(r.l / r.h) : 0.f;
+#pragma unroll
+    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = DD{0.0, 0.0};
+    if (tr.n_table <= kTableCap) {
+      chain_dd(tr, x, [&](int i, const DD& v) {
+        if (i >= kRegPowers) put(i, v);
+      }, [&](const double* h, const float* l) {
+#pragma unroll
+        for (int k = 0; k < kRegPowers; ++k) rp.r[k] = DD{h[k], h[k] * (double)l[k]};
+      });
+    } else {
+      for (int c = 0; c < tr.n_chain; ++c) {
+        const ChainStep st = tr.chain[c];
+        put(st.dst, st.kind == kChainLoad ? DD{coord(x, st.s1), 0.0} : dd_mul(at(st.s1), at(st.s2)));
       }
-      hi[st.dst * stride + col] = h;
-      lo[st.dst * stride + col] = l;
+#pragma unroll
+      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? at(k) : DD{0.0, 0.0};
     }
-    r0 = tr.n_table > 0 ? hi[col] : 0.0;
-    r1 = tr.n_table > 1 ? hi[stride + col] : 0.0;
   }
-  __device__ __forceinline__ double get0() const { return r0; }
-  __device__ __forceinline__ double get1() const { return r1; }
-  __device__ __forceinline__ double get(uint32_t i) const { return hi[i * stride + col]; }
-};
-
-// The fallback reads the powers as double-double (hi + lo).
-struct TabDD : TabF64 {
-  DD d0, d1;
-  __device__ __forceinline__ void build(const DevTree& tr, const double* x) {
-    TabF64::build(tr, x);
-    d0 = tr.n_table > 0 ? dd_at(0) : DD{0.0, 0.0};
-    d1 = tr.n_table > 1 ? dd_at(1) : DD{0.0, 0.0};
+  template <int I>
+  __device__ __forceinline__ DD reg() const { return rp.r[I]; }
+  __device__ __forceinline__ DD get(uint32_t i) const { return at(i); }
+  __device__ __forceinline__ DD getany(uint32_t i) const {
+    return rp.any(i, [&](uint32_t k) { return at(k); });
   }
-  __device__ __forceinline__ DD get0() const { return d0; }
-  __device__ __forceinline__ DD get1() const { return d1; }
-  __device__ __forceinline__ DD get(uint32_t i) const { return dd_at(i); }
 };
 
 struct TabM61 {
-  uint64_t* v;         // [n_table][stride]
-  int col, stride;
-  uint64_t r0, r1;
+  uint64_t* v;         // LDS entries, as TabF64
+  int col, stride, first;
+  RegPow<uint64_t> rp;
   static constexpr size_t bytes_per_entry = kWave * sizeof(uint64_t);
-  __device__ __forceinline__ void bind(char* lds, int, int j, int ppl) {
+  __device__ __forceinline__ void bind(char* lds, int n_table, int j, int ppl) {
     stride = ppl * kWave;
     col = j * kWave + (threadIdx.x & (kWave - 1));
+    first = lds_first(n_table);
     v = (uint64_t*)lds;
   }
+  __device__ __forceinline__ uint64_t& at(uint32_t i) const { return v[(i - first) * stride + col]; }
   __device__ __forceinline__ void build(const DevTree& tr, const uint64_t* x) {
-    for (int c = 0; c < tr.n_chain; ++c) {
-      const ChainStep st = tr.chain[c];
-      v[st.dst * stride + col] =
-          st.kind == kChainLoad ? x[st.s1] : m61_mul(v[st.s1 * stride + col], v[st.s2 * stride + col]);
+#pragma unroll
+    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = 0;
+    if (tr.n_table <= kTableCap) {
+      uint64_t t[kTableCap];
+#pragma unroll
+      for (int i = 0; i < kTableCap; ++i) t[i] = 0;
+      for (int c = 0; c < tr.n_chain; ++c) {
+        const ChainStep st = tr.chain[c];
+        t[st.dst] = st.kind == kChainLoad ? coord(x, st.s1) : m61_mul(t[st.s1], t[st.s2]);
+      }
+#pragma unroll
+      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = t[k];
+      for (int i = kRegPowers; i < tr.n_table; ++i) at(i) = t[i];
+    } else {
+      for (int c = 0; c < tr.n_chain; ++c) {
+        const ChainStep st = tr.chain[c];
+        at(st.dst) = st.kind == kChainLoad ? coord(x, st.s1) : m61_mul(at(st.s1), at(st.s2));
+      }
+#pragma unroll
+      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? at(k) : 0;
     }
-    r0 = tr.n_table > 0 ? v[col] : 0;
-    r1 = tr.n_table > 1 ? v[stride + col] : 0;
   }
-  __device__ __forceinline__ uint64_t get0() const { return r0; }
-  __device__ __forceinline__ uint64_t get1() const { return r1; }
-  __device__ __forceinline__ uint64_t get(uint32_t i) const { return v[i * stride + col]; }
+  template <int I>
+  __device__ __forceinline__ uint64_t reg() const { return rp.r[I]; }
+  __device__ __forceinline__ uint64_t get(uint32_t i) const { return at(i); }
+  __device__ __forceinline__ uint64_t getany(uint32_t i) const {
+    return rp.any(i, [&](uint32_t k) { return at(k); });
+  }
 };
 
 // Three-float powers for the double-float walk: the double-double value of
@@ -364,43 +522,58 @@ __device__ __forceinline__ P3 split3_dd(DD r) {
 }
 
 struct TabP3 {
-  float* f;            // [n_table][3][stride]
-  int col, stride;
-  P3 r0, r1;
+  float* f;            // LDS entries at [(i - first)][3][stride]
+  int col, stride, first;
+  RegPow<P3> rp;
   static constexpr size_t bytes_per_entry = kWave * 3 * sizeof(float);
-  __device__ __forceinline__ void bind(char* lds, int, int j, int ppl) {
+  __device__ __forceinline__ void bind(char* lds, int n_table, int j, int ppl) {
     stride = ppl * kWave;
     col = j * kWave + (threadIdx.x & (kWave - 1));
+    first = lds_first(n_table);
     f = (float*)lds;
   }
   __device__ __forceinline__ P3 load(uint32_t i) const {
-    const float* p = f + i * (3 * stride) + col;
+    const float* p = f + (i - first) * (3 * stride) + col;
     return P3{p[0], p[stride], p[2 * stride]};
   }
-  __device__ __forceinline__ void store(uint32_t i, P3 v) {
-    float* p = f + i * (3 * stride) + col;
+  __device__ __forceinline__ void store(uint32_t i, P3 v) const {
+    float* p = f + (i - first) * (3 * stride) + col;
     p[0] = v.h;
     p[stride] = v.m;
     p[2 * stride] = v.l;
   }
   __device__ __forceinline__ void build(const DevTree& tr, const double* x) {
-    for (int c = 0; c < tr.n_chain; ++c) {
-      const ChainStep st = tr.chain[c];
-      if (st.kind == kChainLoad) {
-        store(st.dst, split3_dd(DD{x[st.s1], 0.0}));
-      } else {
-        const P3 a = load(st.s1), b = load(st.s2);
-        DD r = dd_mul(DD{(double)a.h + (double)a.m, (double)a.l},
-                      DD{(double)b.h + (double)b.m, (double)b.l});
-        store(st.dst, split3_dd(r));
+#pragma unroll
+    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = P3{0.f, 0.f, 0.f};
+    if (tr.n_table <= kTableCap) {
+      chain_dd(tr, x, [&](int i, const DD& v) {
+        if (i >= kRegPowers) store(i, split3_dd(v));
+      }, [&](const double* h, const float* l) {
+#pragma unroll
+        for (int k = 0; k < kRegPowers; ++k) rp.r[k] = split3_dd(DD{h[k], h[k] * (double)l[k]});
+      });
+    } else {
+      // large table: the chain runs on the three-float values in LDS
+      for (int c = 0; c < tr.n_chain; ++c) {
+        const ChainStep st = tr.chain[c];
+        if (st.kind == kChainLoad) {
+          store(st.dst, split3_dd(DD{coord(x, st.s1), 0.0}));
+        } else {
+          const P3 a = load(st.s1), b = load(st.s2);
+          store(st.dst, split3_dd(dd_mul(DD{(double)a.h + (double)a.m, (double)a.l},
+                                         DD{(double)b.h + (double)b.m, (double)b.l})));
+        }
       }
+#pragma unroll
+      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? load(k) : P3{0.f, 0.f, 0.f};
     }
-    r0 = tr.n_table > 0 ? load(0) : P3{0.f, 0.f, 0.f};
-    r1 = tr.n_table > 1 ? load(1) : P3{0.f, 0.f, 0.f};
   }
-  __device__ __forceinline__ P3 get0() const { return r0; }
-  __device__ __forceinline__ P3 get1() const { return r1; }
+  template <int I>
+  __device__ __forceinline__ P3 reg() const { return rp.r[I]; }
   __device__ __forceinline__ P3 get(uint32_t i) const { return load(i); }
+  __device__ __forceinline__ P3 getany(uint32_t i) const {
+    return rp.any(i, [&](uint32_t k) { return load(k); });
+  }
 };
 
 template <class Ar> struct TabFor;
@@ -433,98 +606,132 @@ struct Walker {
   Tab* tab;           // tab[j]: the power table of point j (kernel locals)
   Acc m[DMAX][PPL];
   Acc y[PPL];
+  In xv[OFFT ? PPL : 1][8];   // coordinates by value, for powers computed on the fly
 
-  __device__ __forceinline__ Walker(const In (*x_)[8], Tab* t_) : ops(nullptr), x(x_), tab(t_) {}
+  // coordinate v of point j (j is unrolled; v is wave-uniform)
+  __device__ __forceinline__ In xvar(int j, uint32_t v) const {
+    switch (v) {
+      case 0: return xv[j][0];
+      case 1: return xv[j][1];
+      case 2: return xv[j][2];
+      case 3: return xv[j][3];
+      case 4: return xv[j][4];
+      case 5: return xv[j][5];
+      case 6: return xv[j][6];
+      default: return xv[j][7];
+    }
+  }
+
+  __device__ __forceinline__ Walker(const In (*x_)[8], Tab* t_) : ops(nullptr), x(x_), tab(t_) {
+    if constexpr (OFFT) {
+#pragma unroll
+      for (int j = 0; j < PPL; ++j) {
+#pragma unroll
+        for (int v = 0; v < 8; ++v) xv[j][v] = x_[j][v];
+      }
+    }
+  }
 
 #define FPE_FOR_J _Pragma("unroll") for (int j = 0; j < PPL; ++j)
-  // Apply body(j, X_j) for every point j with the op's power.  The two most
-  // used powers come from registers, the rest from the LDS column; each case
-  // is its own code path.
-#define FPE_WITH_POW(o, BODY)                                              \
-  do {                                                                     \
-    const uint32_t pidx_ = op_pidx((o).info);                              \
-    if (pidx_ == 0) {                                                      \
-      FPE_FOR_J { const Pow X = tab[j].get0(); BODY; }                      \
-    } else if (pidx_ == 1) {                                               \
-      FPE_FOR_J { const Pow X = tab[j].get1(); BODY; }                      \
-    } else if (!OFFT || pidx_ != kOffTable) {                              \
-      FPE_FOR_J { const Pow X = tab[j].get(pidx_); BODY; }                  \
-    } else {                                                               \
-      if constexpr (OFFT) {                                                \
-        FPE_FOR_J { const Pow X = Ar::off_table(x[j], (o)); BODY; }         \
-      }                                                                    \
-    }                                                                      \
-  } while (0)
-
-  // One op at stack depth L (L accumulators open, the top is m[L - 1]).
-  template <int L>
-  __device__ __forceinline__ void step(const Op& o) {
-    const uint32_t info = o.info;
-    if (info & kBitLeaf) {
-      if (info & kBitFirst) {              // LEAF_OPEN: push a * X + b
-        if constexpr (L < DMAX) FPE_WITH_POW(o, m[L][j] = Ar::fma_ab(o, X));
-      } else {                             // LEAF_ADD: top += a * X
-        if constexpr (L >= 1) FPE_WITH_POW(o, m[L - 1][j] = Ar::fma_ca(o, X, m[L - 1][j]));
+  // X for point j in power class PC (see PowClass): registers, one LDS
+  // entry, or (class 3) the product of two entries / computed on the fly.
+  template <uint32_t PC>
+  __device__ __forceinline__ Pow power(const Op& o, int j) const {
+    if constexpr (PC < (uint32_t)kRegPowers) {
+      return tab[j].template reg<(int)PC>();
+    } else if constexpr (PC == kPowLds) {
+      return tab[j].get(op_pidx(o.info));
+    } else {
+      const uint32_t p1 = op_pidx(o.info), p2 = op_pidx2(o.info);
+      if (p2 != kNoPair) {
+        const Pow a = Ar::pair(tab[j].getany(p1), tab[j].getany(p2));
+        if (op_deg(o.deg) & kThirdBit) return Ar::pair(a, tab[j].getany(op_deg(o.deg) & 0xFFu));
+        return a;
       }
-    } else if (info & kBitFirst) {         // NODE_OPEN: top = top * X + b
-      if constexpr (L >= 1) FPE_WITH_POW(o, m[L - 1][j] = Ar::fma_tb(m[L - 1][j], X, o));
-    } else {                               // NODE_ADD: below += top * X; pop
-      if constexpr (L >= 2) FPE_WITH_POW(o, m[L - 2][j] = Ar::fma_tt(m[L - 1][j], X, m[L - 2][j]));
+      if constexpr (OFFT) return Ar::off_table(xvar(j, op_var(o.info)), o);
+      return tab[j].getany(p1);
+    }
+  }
+
+  // One op with dispatch code C: depth L (L accumulators open, the top is
+  // m[L - 1]), kind K, power class PC.
+  template <uint32_t C>
+  __device__ __forceinline__ void step(const Op& o) {
+    constexpr int L = (int)(C & 15u);
+    constexpr uint32_t K = (C >> 4) & 3u;
+    constexpr uint32_t PC = C >> 6;
+    if constexpr (K == kLeafOpen) {              // push a * X + b
+      if constexpr (L < DMAX) {
+        FPE_FOR_J { m[L][j] = Ar::fma_ab(o, power<PC>(o, j)); }
+      }
+    } else if constexpr (K == kLeafAdd) {         // top += a * X
+      if constexpr (L >= 1 && L <= DMAX) {
+        FPE_FOR_J { m[L - 1][j] = Ar::fma_ca(o, power<PC>(o, j), m[L - 1][j]); }
+      }
+    } else if constexpr (K == kNodeOpen) {        // top = top * X + b
+      if constexpr (L >= 1 && L <= DMAX) {
+        FPE_FOR_J { m[L - 1][j] = Ar::fma_tb(m[L - 1][j], power<PC>(o, j), o); }
+      }
+    } else {                                      // NODE_ADD: below += top * X; pop
+      if constexpr (L >= 2 && L <= DMAX) {
+        FPE_FOR_J { m[L - 2][j] = Ar::fma_tt(m[L - 1][j], power<PC>(o, j), m[L - 2][j]); }
+      }
     }
   }
 
   // The root: y = (children ? m[0] : a) * X_root.
+  template <uint32_t PC>
   __device__ __forceinline__ void finish(const Op& o) {
     const uint32_t info = o.info;
     FPE_FOR_J { y[j] = m[0][j]; }
     if (info & kEndLeafRoot) {
       FPE_FOR_J { y[j] = Ar::leaf_root(o); }
     }
-    if (info & kEndHasPow) FPE_WITH_POW(o, y[j] = Ar::mul(y[j], X));
+    if (info & kEndHasPow) {
+      FPE_FOR_J { y[j] = Ar::mul(y[j], power<PC>(o, j)); }
+    }
   }
 
-  // The walk: one flat loop over the ops; the op's depth (set by the host)
-  // selects the code with the right compile-time accumulator indices.
+  // The walk: one flat loop over the ops and one switch on the op's dispatch
+  // code (set by the host), whose cases carry compile-time accumulator
+  // indices.
   __device__ __forceinline__ void walk() {
-    int pc = 0;
+    const Op* __restrict__ op = ops;
 #pragma unroll 1
     for (;;) {
-      const Op o = ops[pc];
-      ++pc;
-      const uint32_t info = o.info;
-      if (info & kBitEnd) {
-        finish(o);
-        return;
-      }
-      const uint32_t L = op_level(info);
-      {
-        switch (L) {
-          case 0: step<0>(o); break;
-          case 1: step<1>(o); break;
-          case 2: step<2>(o); break;
-          case 3: step<3>(o); break;
-          case 4: step<4>(o); break;
-          case 5: step<5>(o); break;
-          case 6: step<6>(o); break;
-          case 7: step<7>(o); break;
-          default:
-            if constexpr (DMAX > 8) {
-              switch (L) {
-          case 8: step<8>(o); break;
-          case 9: step<9>(o); break;
-          case 10: step<10>(o); break;
-          case 11: step<11>(o); break;
-          case 12: step<12>(o); break;
-          case 13: step<13>(o); break;
-          case 14: step<14>(o); break;
-          default: step<15>(o); break;
-              }
-            }
-        }
+      const Op o = *op;
+      ++op;
+      switch (op_code(o.deg)) {
+#define FPE_END(c) \
+  case c: finish<((c) >> 6)>(o); return;
+#define FPE_OP(c)                                                          \
+  case c:                                                                  \
+    if constexpr (((c) & 15) < (DMAX > 8 ? 16 : 8)) step<(c)>(o);          \
+    break;
+#define FPE_L(k, p)                                                        \
+  FPE_OP(1 + 16 * (k) + 64 * (p)) FPE_OP(2 + 16 * (k) + 64 * (p))          \
+  FPE_OP(3 + 16 * (k) + 64 * (p)) FPE_OP(4 + 16 * (k) + 64 * (p))          \
+  FPE_OP(5 + 16 * (k) + 64 * (p)) FPE_OP(6 + 16 * (k) + 64 * (p))          \
+  FPE_OP(7 + 16 * (k) + 64 * (p)) FPE_OP(8 + 16 * (k) + 64 * (p))          \
+  FPE_OP(9 + 16 * (k) + 64 * (p)) FPE_OP(10 + 16 * (k) + 64 * (p))         \
+  FPE_OP(11 + 16 * (k) + 64 * (p)) FPE_OP(12 + 16 * (k) + 64 * (p))        \
+  FPE_OP(13 + 16 * (k) + 64 * (p)) FPE_OP(14 + 16 * (k) + 64 * (p))        \
+  FPE_OP(15 + 16 * (k) + 64 * (p))
+#define FPE_P(p)                                                           \
+  FPE_END(64 * (p)) FPE_L(0, p)                                            \
+  FPE_OP(16 + 64 * (p)) FPE_L(1, p)                                        \
+  FPE_OP(32 + 64 * (p)) FPE_L(2, p)                                        \
+  FPE_OP(48 + 64 * (p)) FPE_L(3, p)
+        FPE_P(0) FPE_P(1) FPE_P(2) FPE_P(3) FPE_P(4) FPE_P(5)
+#undef FPE_P
+#undef FPE_L
+#undef FPE_OP
+#undef FPE_END
+        default:
+          break;
       }
     }
   }
-#undef FPE_WITH_POW
 #undef FPE_FOR_J
 
   __device__ __forceinline__ void run(const DevTree& tr) {
