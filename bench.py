@@ -1,16 +1,22 @@
 """Benchmark of the evaluation-tree hot path on one MI355X.
 
-Workload (timed step): the sparse univariate workload of degrees 3000 and
-5000 (coefficients U[-1, 1], 10 % of the exponents below the degree zeroed),
+Timed step: the sparse univariate workload of degrees 3000 and 5000
+(coefficients U[-1, 1], 10 % of the exponents below the degree zeroed),
 1e7 points U[-1.05, 1.05] resident in HBM, each degree under the balanced,
 Estrin and Hörner schemes, each in the served form (compensated FP32 with a
 running error bound and FP64 re-evaluation of flagged points) and in plain
-FP64: 12 evaluations, 4.32e11 term-evaluations per step.  Trees are compiled
+FP64: 12 evaluations, 8.1e11 term-evaluations per step.  Trees are compiled
 and uploaded once, before the timed region.
 
-Prints one JSON line (see the "roofline" and "cpu_baseline" objects): the
-value is whole-step term-evaluations per second; the accuracy of the last
-step against the CPU oracle is checked on a sample after the timed region.
+After the timed region (not part of ``value``): the accuracy of the last step
+against the CPU oracle on a sample; a served stream (Poisson arrivals of
+uneven evaluate requests through the continuous-batching server) for p50/p99
+latency; the exact mod 2^61-1 trivariate workload and the batched
+composition mod 2^31-1, each timed beside the main line; and the CPU oracle
+timed on a bounded sample of the step's workload.
+
+Prints one JSON line; ``roofline`` describes the dominant kernel (the
+compensated-FP32 walk), ``roofline_f64`` the plain FP64 walk.
 """
 from __future__ import annotations
 
@@ -25,13 +31,16 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks and unit counts
+# MI355X published peaks and unit counts.  FP32 vector 157.3 TFLOP/s counts
+# an FMA as two flops: 256 CU x 128 FP32 lanes x 2.4 GHz = 78.6e12 FP32 VALU
+# lane-instructions/s.  FP64 vector 78.6 TFLOP/s = 39.3e12 FP64 FMA/s.
 HBM_PEAK_GBS = 8000.0
-N_CU, CLOCK_GHZ, LANES_PER_CU = 256, 2.4, 64
-VALU_LANE_OPS = N_CU * LANES_PER_CU * CLOCK_GHZ * 1e9      # 3.93e13 lane-instructions/s
-FP64_FMA_PEAK = 78.6e12 / 2                                # FMA/s
-DF32_OPS_PER_TERM = 16      # FP32 VALU ops of one double-float multiply-add (TwoProd,
-                            # 3 cross-term fmas, TwoSum, 2 adds, FastTwoSum)
+FP32_VALU_PEAK = 256 * 128 * 2.4e9
+FP64_FMA_PEAK = 256 * 64 * 2.4e9
+# FP32 operations of one compensated multiply-add a * X + b: product and its
+# error by fma (2), three cross terms (3), TwoSum (6), two low-order adds (2),
+# FastTwoSum (3), running error bound (3 fma) and condition sum (1 fma).
+DF32_OPS_PER_TERM = 20
 
 
 def log(msg):
@@ -63,6 +72,114 @@ class HipEvents:
         return float(ms.value)
 
 
+def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, load: float):
+    """Poisson arrivals of uneven evaluate requests (compensated FP32 with FP64
+    fallback) through the server: first all at once to find the saturation
+    request rate, then arrivals at ``load`` times that rate for latency."""
+    reqs = fpe_inputs.served_stream(nreq, rate_per_s=1.0)   # unit-rate arrival times, rescaled below
+    prepared = []
+    for r in reqs:
+        m = r.poly
+        t = fpe.Tree(m.exps, m.coeffs, r.scheme, fpe.F32C).upload(dev)
+        pts = [torch.from_numpy(np.ascontiguousarray(m.points[j])).to(dev) for j in range(m.points.shape[0])]
+        out = torch.empty(m.points.shape[1], dtype=torch.float64, device=dev)
+        prepared.append((r.arrival_s, t, pts, out, m))
+    torch.cuda.synchronize()
+    budget = 2 << 30
+
+    srv = fpe.Server(hbm_budget=budget, max_inflight=64)
+    t0 = time.perf_counter()
+    for _, t, pts, out, _ in prepared:
+        srv.submit(t, pts, out, domain=fpe.F32C)
+    srv.drain()
+    wall_sat = time.perf_counter() - t0
+    st = srv.stats()
+    sat = {"requests": nreq, "wall_s": wall_sat, "term_evals": st.term_evals,
+           "term_evals_per_s": st.term_evals / wall_sat, "batches": st.batches,
+           "fallback_frac": st.fallback_frac}
+    srv.close()
+    sat_rps = nreq / wall_sat
+
+    rate = load * sat_rps
+    scale = 1.0 / rate
+    srv = fpe.Server(hbm_budget=budget, max_inflight=64)
+    t0 = time.perf_counter()
+    for at, t, pts, out, _ in prepared:
+        target = t0 + at * scale
+        while True:
+            now = time.perf_counter()
+            if now >= target:
+                break
+            if target - now > 2e-4:
+                time.sleep((target - now) * 0.5)
+        srv.submit(t, pts, out, domain=fpe.F32C)
+    srv.drain()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    lat = {"load": load, "rate_rps": rate, "requests": nreq, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
+           "mean_ms": st.mean_ms, "batches": st.batches, "term_evals_per_s": st.term_evals / wall,
+           "fallback_frac": st.fallback_frac}
+    srv.close()
+
+    # every served result against the oracle on a sample of its points
+    from oracle import exact
+    worst = 0.0
+    for _, _, _, out, m in prepared[:: max(1, nreq // 24)]:
+        y = out.cpu().numpy()
+        idx = np.arange(0, len(y), max(1, len(y) // 64))
+        ref = exact.dd_monomial_sum(m.exps, m.coeffs, m.points[:, idx])
+        worst = max(worst, float(np.max(np.abs(y[idx] - ref) / np.abs(ref))))
+    lat["max_rel_err_sampled"] = worst
+    return sat, lat
+
+
+def modp_phase(fpe, fpe_inputs, torch, dev, hev, reps: int = 3):
+    """Exact trivariate evaluation mod 2^61-1 (12,341 terms, 1e6 points)."""
+    inp = fpe_inputs.trivariate()
+    pts = [torch.from_numpy(np.ascontiguousarray(inp.points[j])).to(dev) for j in range(3)]
+    res = {}
+    for s in ("balanced", "estrin", "horner"):
+        t = fpe.Tree(inp.exps, inp.coeffs, s, fpe.MODP, fpe.P61).upload(dev)
+        out = torch.empty(inp.points.shape[1], dtype=torch.int64, device=dev)
+        fpe.evaluate(t, pts, out=out)
+        ms = []
+        for _ in range(reps):
+            e0, e1 = hev.create(), hev.create()
+            fpe.evaluate(t, pts, out=out, events=(e0, e1))
+            torch.cuda.synchronize()
+            ms.append(hev.elapsed_ms(e0, e1))
+        m = float(np.median(ms))
+        res[s] = {"walk_ms": m, "term_evals_per_s": len(inp.coeffs) * inp.points.shape[1] / (m * 1e-3)}
+    return res
+
+
+def compose_phase(fpe, fpe_inputs, torch, dev, reps: int = 3):
+    """4096 instances of p(q(x)) mod 2^31-1, deg p = 255, deg q = 15."""
+    inp = fpe_inputs.compose_batch()
+    b, dp1 = inp.p.shape
+    ex = np.arange(dp1, dtype=np.int32).reshape(-1, 1)
+    q = torch.from_numpy(np.ascontiguousarray(inp.q.astype(np.int32))).to(dev)
+    res = {}
+    for s in ("balanced", "estrin", "horner"):
+        t = fpe.Tree(ex, inp.p.astype(np.uint64), s, fpe.MODP, fpe.P31).upload(dev)
+        out = fpe.compose(t, q)
+        ws = torch.empty(int(fpe.lib.fpe_compose_workspace_bytes(t.handle, inp.q.shape[1] - 1)) + 256,
+                         dtype=torch.uint8, device=dev)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fpe.compose(t, q, out=out, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        m = float(np.median(ms))
+        res[s] = {"ms": m, "instances_per_s": b / (m * 1e-3)}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -70,11 +187,13 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--points", type=int, default=10_000_000)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-points", type=int, default=400_000)
+    ap.add_argument("--cpu-points", type=int, default=600_000)
+    ap.add_argument("--no-extra", action="store_true", help="skip the served, mod-p and composition phases")
+    ap.add_argument("--served-requests", type=int, default=400)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this benchmark runs on one GPU only; the evaluate path "
-                          "shards by point range without communication (see DESIGN.md)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; the evaluation shards by "
+                          "point range without communication, so more GPUs are not measured here"}))
         sys.exit(2)
 
     import torch
@@ -139,12 +258,13 @@ def main():
     walk_ms = {k: float(np.mean([hev.elapsed_ms(a, b) for a, b in ev[k]])) for k in keys}
     per = {}
     for fname, _ in forms:
-        ks = [k for k in keys if k[2] == fname]
         per[fname] = {f"n{k[0]}_{k[1]}": {"walk_ms": round(walk_ms[k], 4),
-                                           "term_evals_per_s": term_evals[k] / (walk_ms[k] * 1e-3)}
-                      for k in ks}
+                                           "term_evals_per_s": term_evals[k] / (walk_ms[k] * 1e-3),
+                                           "n_table": int(trees[k].info.n_table),
+                                           "walk_depth": int(trees[k].info.walk_depth)}
+                      for k in keys if k[2] == fname}
 
-    # dominant kernel: the double-float walk (most of the step's time)
+    # dominant kernel: the compensated-FP32 walk (most of the step's time)
     df_keys = [k for k in keys if k[2] == "f32c"]
     df_ops = sum(term_evals[k] * DF32_OPS_PER_TERM for k in df_keys)
     df_time = sum(walk_ms[k] for k in df_keys) * 1e-3
@@ -152,22 +272,24 @@ def main():
     f64_fma = sum(term_evals[k] for k in f64_keys)
     f64_time = sum(walk_ms[k] for k in f64_keys) * 1e-3
     roofline = {
-        "kernel": "k_eval_df32 (compensated FP32 walk)",
+        "kernel": "k_eval_df32 (compensated FP32 walk), 6 launches per step",
         "bound": "alu",
         "achieved": df_ops / df_time / 1e12,
-        "peak": VALU_LANE_OPS / 1e12,
+        "peak": FP32_VALU_PEAK / 1e12,
         "unit": "TOP/s (FP32 VALU lane-ops)",
-        "frac": (df_ops / df_time) / VALU_LANE_OPS,
+        "frac": (df_ops / df_time) / FP32_VALU_PEAK,
         "traffic": None,
         "ops_per_term_eval": DF32_OPS_PER_TERM,
+        "avg_launch_ms": df_time * 1e3 / len(df_keys),
     }
     roofline_f64 = {
-        "kernel": "k_eval_f64 (plain FP64 walk)",
+        "kernel": "k_eval_f64 (plain FP64 walk), 6 launches per step",
         "bound": "alu",
         "achieved": f64_fma / f64_time / 1e12,
         "peak": FP64_FMA_PEAK / 1e12,
         "unit": "T FMA/s (FP64)",
         "frac": (f64_fma / f64_time) / FP64_FMA_PEAK,
+        "avg_launch_ms": f64_time * 1e3 / len(f64_keys),
     }
 
     # accuracy of the last step on a sample (outside the timed region)
@@ -187,22 +309,42 @@ def main():
                                 "f64_max_scaled_err": float(np.max(np.abs(y64 - ref) / pt))}
             fb[f"n{n}_{s}"] = nfb[(n, s)].item() / args.points
 
+    # free the main workload before the side phases
+    del trees, outs, ws, xs
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+    served = latency = modp = compose = None
+    if not args.no_extra:
+        log("served stream")
+        served, latency = served_phase(fpe, fpe_inputs, torch, dev, args.served_requests, load=0.8)
+        log("mod-p trivariate")
+        modp = modp_phase(fpe, fpe_inputs, torch, dev, hev)
+        log("composition")
+        compose = compose_phase(fpe, fpe_inputs, torch, dev)
+
     cpu = None
     if not args.no_cpu:
-        # the CPU oracle as it stands: plain FP64 Hörner over the dense
-        # coefficient vector, OpenMP over points, on the host's cores
+        # the CPU oracle as it stands (C, -O2, OpenMP over points): the
+        # double-double Hörner that the compensated results are checked
+        # against and the plain FP64 Hörner, each over the dense coefficient
+        # vector, on the first cpu_points points of both degrees
+        log("cpu oracle")
         native.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
         cores = native.threads()
         te = 0.0
         c0 = time.perf_counter()
         for n in degrees:
-            xs_c = inputs[n].points[: args.cpu_points]
+            xs_c = np.ascontiguousarray(inputs[n].points[: args.cpu_points])
+            nnz = float(np.count_nonzero(inputs[n].coeffs))
+            native.dd_value(inputs[n].coeffs, xs_c)
             native.horner_f64(inputs[n].coeffs, xs_c, use_fma=False)
-            te += float(np.count_nonzero(inputs[n].coeffs)) * len(xs_c)
+            te += 2 * nnz * len(xs_c)
         c1 = time.perf_counter()
         cpu = {"value": te / (c1 - c0), "unit": "term-evals/s", "cores": cores, "kind": "oracle",
-               "sample": f"plain FP64 Hörner (C, -O2, OpenMP) on the first {args.cpu_points} points of "
-                         f"degrees 3000 and 5000 ({te:.3g} term-evals, {c1 - c0:.2f} s)"}
+               "sample": f"double-double and plain FP64 Hörner (C, -O2, OpenMP) on the first "
+                         f"{args.cpu_points} points of degrees 3000 and 5000 ({te:.3g} term-evals, "
+                         f"{c1 - c0:.2f} s)"}
 
     out = {
         "metric": "term-evals/sec at stated rel. error vs FP64 oracle; p50/p99 request latency",
@@ -215,7 +357,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32 (double-float) + f64",
+        "dtype": "f32 double-float (f64 fallback) + f64",
         "data": "synthetic",
         "config": {"workload": "sparse univariate, degrees 3000 and 5000, 10% zero coefficients, "
                                "1e7 points U[-1.05,1.05]; schemes balanced/Estrin/Hörner; compensated "
@@ -227,7 +369,10 @@ def main():
         "per_evaluation": per,
         "accuracy_sampled": acc,
         "fallback_frac": fb,
-        "latency_ms": None,
+        "latency_ms": None if latency is None else {"p50": latency["p50_ms"], "p99": latency["p99_ms"]},
+        "served": None if served is None else {"saturation": served, "poisson": latency},
+        "modp_trivariate": modp,
+        "compose_4096": compose,
     }
     print(json.dumps(out), flush=True)
 

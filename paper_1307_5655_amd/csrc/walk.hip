@@ -33,7 +33,13 @@ inline int64_t blocks_for(int64_t n, int ppl) { return (n + kBlock * ppl - 1) / 
 // multiply-adds); the heavier double-float and modular steps take 1.
 int pick_ppl(const fpe_tree* t, const fpe_eval_opts* opts) {
   if (t->n_offtable > 0) return 1;
-  int p = opts && opts->points_per_lane > 0 ? opts->points_per_lane : (t->domain == FPE_F64 ? 2 : 1);
+  // Default: a chain-like walk (depth <= 2, e.g. Hörner) keeps few
+  // accumulators and gains from more points per lane (4 FP64, 2 otherwise);
+  // deeper walks spend those registers on the stack (2 FP64, 1 otherwise).
+  const bool shallow = t->depth <= 2;
+  int p = opts && opts->points_per_lane > 0 ? opts->points_per_lane
+          : t->domain == FPE_F64               ? (shallow ? 4 : 2)
+                                               : (shallow ? 2 : 1);
   if (t->depth > 8) p = std::min(p, t->domain == FPE_F64 ? 2 : 1);
   if (t->domain != FPE_F64) p = std::min(p, 2);
   return p >= 4 ? 4 : p >= 2 ? 2 : 1;
