@@ -523,10 +523,12 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
   for (auto& kv : freq) byf.push_back({kv.second, kv.first});
   std::stable_sort(byf.begin(), byf.end(), [](auto& a, auto& b) { return a.first > b.first; });
   // The table holds the most used powers and the chain temporaries they
-  // need, within a cap (16 entries for the pointwise walks, so the per-point
-  // table stays small in LDS); a power left out is read as the product of two
-  // entries when its degree is the sum of two table degrees, else computed
-  // on the fly.  A batch tree (composition) keeps its coefficients per
+  // need, within a cap; a power left out is read as the product of two (or
+  // three) entries when its degree is such a sum, else computed on the fly.
+  // The per-point table lives in private memory and only its first entries
+  // in registers, so a larger table costs little: the smallest of 16, 24,
+  // 32, 48 entries is taken that covers every power with at most 1 in 64
+  // walk steps reading a product.  A batch tree (composition) keeps its coefficients per
   // instance, so its ops carry node indices instead of coefficient values,
   // and its table may hold up to 48 entries without products.
   const bool index_ops = domain == FPE_MODP && modulus == kP31;
@@ -539,23 +541,21 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
       if (tmp.ok) plan = std::move(tmp);
     }
   } else {
-    // 16 entries keep the per-point table small; a tree whose powers cannot
-    // all be covered (directly or as products) within 16 gets 24, 32 or 48
     std::map<std::pair<int32_t, int32_t>, int64_t> fr(freq.begin(), freq.end());
-    // A few walk steps may compute their power on the fly instead (at most
-    // 1 in 256 steps) rather than double the table.
     int64_t nsteps = 0;
     for (auto& kv : fr) nsteps += kv.second;
     for (int32_t c : {16, 24, 32, kMaxTable}) {
       CoverPlan cp;
       cp.build(fr, c);
-      int64_t missing = 0;
-      for (auto& kv : fr)
+      int64_t missing = 0, products = 0;
+      for (auto& kv : fr) {
         if (!cp.covered(kv.first.first, kv.first.second)) missing += kv.second;
+        else if (!cp.index.count(kv.first)) products += kv.second;
+      }
       plan.entries = cp.entries;
       plan.chain = cp.chain;
       plan.index = cp.index;
-      if (missing == 0 || (c == 16 && missing * 256 <= nsteps)) break;
+      if (missing == 0 && products * 64 <= nsteps) break;
     }
   }
   std::vector<std::pair<int32_t, int32_t>> pending;

@@ -7,13 +7,12 @@ namespace fpe {
 template <int DMAX, int PPL, bool OFFT>
 __global__ __launch_bounds__(kBlock) void k_eval_df32(DevTree tr, Pts<double> P, int64_t npts,
                                                       F32COut o) {
-  extern __shared__ __align__(16) char lds[];
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t base = (int64_t)blockIdx.x * kBlock * PPL + threadIdx.x;
   double x[PPL][8];
   load_points<double, PPL>(P, tr.nvars, base, npts, x);
   DF r[PPL];
-  walk_points<ArDF32, DMAX, PPL, OFFT>(tr, x, lds, r);
+  walk_points<ArDF32, DMAX, PPL, OFFT>(tr, x, r);
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
     const int64_t i = base + (int64_t)j * kWave;
@@ -44,7 +43,6 @@ __global__ __launch_bounds__(kBlock) void k_fallback_dd(DevTree tr, Pts<double> 
                                                         const int32_t* __restrict__ list,
                                                         const int64_t* __restrict__ count,
                                                         double* __restrict__ out) {
-  extern __shared__ __align__(16) char lds[];
   const int64_t n = *count;
   for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
     const int64_t k = base + threadIdx.x;
@@ -52,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_fallback_dd(DevTree tr, Pts<double> 
     const int64_t i = k < n ? list[k] : -1;
 #pragma unroll
     for (int v = 0; v < 8; ++v) x[v] = (i >= 0 && v < tr.nvars) ? P.p[v][i] : 0.0;
-    const DD r = walk_point<ArDD, DMAX, OFFT>(tr, x, lds);
+    const DD r = walk_point<ArDD, DMAX, OFFT>(tr, x);
     if (i >= 0) out[i] = r.h + r.l;
   }
 }
@@ -61,7 +59,7 @@ template <int DMAX, int PPL, bool OFFT>
 static void go(const KernelLaunch& L, const F32COut& o) {
   Pts<double> P{};
   for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const double*)L.pts[j];
-  hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), L.lds,
+  hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), 0,
                      L.stream, L.tr, P, L.npts, o);
 }
 
@@ -80,7 +78,7 @@ template <int DMAX, bool OFFT>
 static void gofb(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out) {
   Pts<double> P{};
   for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const double*)L.pts[j];
-  hipLaunchKernelGGL((k_fallback_dd<DMAX, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), L.lds,
+  hipLaunchKernelGGL((k_fallback_dd<DMAX, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), 0,
                      L.stream, L.tr, P, list, count, out);
 }
 

@@ -176,7 +176,8 @@ fpe_status launch_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint
 size_t compose_workspace_bytes(const fpe_tree* t, int32_t dq);
 constexpr int kMaxDepth = 16;   // stack depth the kernels hold (4 bits of the code)
 constexpr int kMaxTable = 48;   // power-table entries held per point (composition)
-constexpr int kTableCap = 16;   // power-table entries per point for the pointwise walks
+constexpr int kTableCap = 16;   // tables up to this size are built by the register chain
+constexpr int kTableCapMulti = 32;   // largest table of the kernels with several points per lane
 constexpr int kMaxServe = 256;  // requests per fused launch
 constexpr int kServeGrid = 4096;   // fixed grid of the fused kernels (workgroups)
 // Fused served launch (walk.hip).
@@ -194,8 +195,6 @@ __host__ __device__ inline int64_t* table_prefix(WorkTable* t) {
   return (int64_t*)(table_items(t) + kMaxServe);
 }
 __host__ __device__ inline int64_t* table_counters(WorkTable* t) { return table_prefix(t) + kMaxServe + 1; }
-constexpr int kLdsFallback = 3;
-size_t lds_bytes(const fpe_tree* t, int kind);
 
 // One pointwise launch (walk.hip picks the shape; the eval_*.hip files hold
 // the kernels).
@@ -204,7 +203,6 @@ struct KernelLaunch {
   const void* pts[8];
   int64_t npts;
   int64_t nblocks;
-  size_t lds;
   hipStream_t stream;
   int ppl;
   bool offt;

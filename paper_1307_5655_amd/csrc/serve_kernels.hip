@@ -23,7 +23,6 @@ __global__ void k_serve_zero(WorkTable* wt) {
 
 template <int DMAX>
 __global__ __launch_bounds__(kBlock) void k_serve_walk(WorkTable* wt) {
-  extern __shared__ __align__(16) char lds[];
   const int n = wt->n_items;
   const int64_t total = wt->total_blocks;
   const WorkItem* items = table_items(wt);
@@ -39,10 +38,10 @@ __global__ __launch_bounds__(kBlock) void k_serve_walk(WorkTable* wt) {
     for (int j = 0; j < 8; ++j) x[j] = (in && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
     bool flag = false;
     if (it.domain == FPE_F64) {
-      const double y = walk_point<ArF64, DMAX, true>(it.tree, x, lds);
+      const double y = walk_point<ArF64, DMAX, true>(it.tree, x);
       if (in) it.out[i] = y;
     } else {
-      const DF rr = walk_point<ArDF32, DMAX, true>(it.tree, x, lds);
+      const DF rr = walk_point<ArDF32, DMAX, true>(it.tree, x);
       if (in) {
         double y;
         float cond;
@@ -57,7 +56,6 @@ __global__ __launch_bounds__(kBlock) void k_serve_walk(WorkTable* wt) {
 
 template <int DMAX>
 __global__ __launch_bounds__(kBlock) void k_serve_fallback(WorkTable* wt) {
-  extern __shared__ __align__(16) char lds[];
   const int n = wt->n_items;
   const WorkItem* items = table_items(wt);
   const int64_t* counters = table_counters(wt);
@@ -71,7 +69,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_fallback(WorkTable* wt) {
       double x[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) x[j] = (i >= 0 && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
-      const DD rr = walk_point<ArDD, DMAX, true>(it.tree, x, lds);
+      const DD rr = walk_point<ArDD, DMAX, true>(it.tree, x);
       if (i >= 0) it.out[i] = rr.h + rr.l;
     }
   }

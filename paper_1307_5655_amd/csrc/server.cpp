@@ -8,8 +8,8 @@
 // as one fused launch per table, replayed from a HIP graph whose nodes are
 //   copy host table -> device, zero the fallback counters, fused walk (x2),
 //   fused FP64 fallback (x2), copy counters device -> host.
-// Only the kernels' dynamic LDS size changes between batches (patched with
-// hipGraphExecKernelNodeSetParams).  Two batch slots alternate, so the next
+// The graph is built once per slot and replayed unchanged: a batch is
+// described entirely by the work table it copies in.  Two batch slots alternate, so the next
 // batch is admitted and staged while the previous one runs; requests that
 // arrive meanwhile join the next batch.  Each point's result depends only on
 // its own walk, so a request's output is the same alone and in any mix.
@@ -101,8 +101,6 @@ struct Slot {
   int64_t* host_counters[2] = {nullptr, nullptr};   // pinned copy-back
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipGraphNode_t walk_node[2] = {nullptr, nullptr}, fb_node[2] = {nullptr, nullptr};
-  hipKernelNodeParams walk_p[2], fb_p[2];
   void* args[2][1];
   WorkTable* argv[2];
   hipEvent_t done_ev = nullptr;
@@ -178,7 +176,7 @@ fpe_status build_slot(fpe_server* s, Slot& sl) {
     wp.func = (void*)(c == 0 ? K.walk8 : K.walk16);
     wp.gridDim = dim3(kServeGrid);
     wp.blockDim = dim3(64);
-    wp.sharedMemBytes = 16;
+    wp.sharedMemBytes = 0;
     wp.kernelParams = sl.args[c];
     if (hipGraphAddKernelNode(&w, sl.graph, &z, 1, &wp) != hipSuccess)
       return fail(FPE_EDEVICE, "server: graph kernel node failed");
@@ -190,10 +188,6 @@ fpe_status build_slot(fpe_server* s, Slot& sl) {
     if (hipGraphAddMemcpyNode1D(&back, sl.graph, &f, 1, sl.host_counters[c], table_counters(sl.dev[c]),
                                 sizeof(int64_t) * kMaxServe, hipMemcpyDeviceToHost) != hipSuccess)
       return fail(FPE_EDEVICE, "server: graph memcpy node failed");
-    sl.walk_node[c] = w;
-    sl.fb_node[c] = f;
-    sl.walk_p[c] = wp;
-    sl.fb_p[c] = fp;
   }
   if (hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0) != hipSuccess)
     return fail(FPE_EDEVICE, "server: hipGraphInstantiate failed");
@@ -205,7 +199,6 @@ fpe_status build_slot(fpe_server* s, Slot& sl) {
 bool try_launch(fpe_server* s, Slot& sl) {
   sl.tickets[0].clear();
   sl.tickets[1].clear();
-  size_t lds[2] = {16, 16};
   int n[2] = {0, 0};
   int64_t blocks[2] = {0, 0};
   while (!s->queue.empty() && s->inflight < s->max_inflight) {
@@ -231,7 +224,6 @@ bool try_launch(fpe_server* s, Slot& sl) {
     it.domain = q.r.domain;
     table_prefix(sl.host[c])[n[c]] = blocks[c];
     blocks[c] += (q.r.npts + 63) / 64;
-    lds[c] = std::max(lds[c], lds_bytes(q.r.tree, kLdsFallback));
     sl.tickets[c].push_back(q.ticket);
     n[c]++;
   }
@@ -240,11 +232,6 @@ bool try_launch(fpe_server* s, Slot& sl) {
     sl.host[c]->n_items = n[c];
     sl.host[c]->total_blocks = blocks[c];
     table_prefix(sl.host[c])[n[c]] = blocks[c];
-    sl.walk_p[c].sharedMemBytes = (unsigned)lds[c];
-    sl.fb_p[c].sharedMemBytes = (unsigned)lds[c];
-    hipError_t e1 = hipGraphExecKernelNodeSetParams(sl.exec, sl.walk_node[c], &sl.walk_p[c]);
-    hipError_t e2 = hipGraphExecKernelNodeSetParams(sl.exec, sl.fb_node[c], &sl.fb_p[c]);
-    if (e1 != hipSuccess || e2 != hipSuccess) s->dev_err = "server: graph parameter update failed";
   }
   if (hipGraphLaunch(sl.exec, s->stream) != hipSuccess || hipEventRecord(sl.done_ev, s->stream) != hipSuccess)
     s->dev_err = "server: graph launch failed";

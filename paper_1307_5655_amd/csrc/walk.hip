@@ -7,18 +7,6 @@ namespace fpe {
 
 __global__ void k_zero_i64(int64_t* p) { *p = 0; }
 
-// LDS of one wavefront's power table (one point per lane) for a kernel kind:
-// FPE_F64, FPE_F32C (three-float powers), FPE_MODP, or kLdsFallback (the
-// double-double re-evaluation; also the size every served kernel reserves).
-size_t lds_bytes(const fpe_tree* t, int kind) {
-  size_t per = kind == FPE_MODP ? TabM61::bytes_per_entry
-             : kind == FPE_F32C ? TabP3::bytes_per_entry
-             : kind == kLdsFallback ? std::max(TabDD::bytes_per_entry, TabP3::bytes_per_entry)
-             : t->n_table > kTableCap ? TabF64::bytes_per_entry_big
-                                    : TabF64::bytes_per_entry;
-  return std::max<size_t>(16, per * (size_t)lds_entries(t->n_table));
-}
-
 size_t eval_workspace_bytes(const fpe_tree* t, int64_t npts) {
   if (!t || t->domain != FPE_F32C) return 0;
   // [count int64 | pad to 256 | list int32[npts]]
@@ -29,17 +17,16 @@ namespace {
 
 inline int64_t blocks_for(int64_t n, int ppl) { return (n + kBlock * ppl - 1) / (kBlock * ppl); }
 
-// Points per lane: FP64 walks take 2 (an op drives two independent fused
-// multiply-adds); the heavier double-float and modular steps take 1.
+// Points per lane: one op drives PPL independent multiply-adds, which
+// amortises the wave-uniform dispatch; tables beyond kTableCapMulti entries
+// and trees with on-the-fly powers use the one-point kernels.
 int pick_ppl(const fpe_tree* t, const fpe_eval_opts* opts) {
-  if (t->n_offtable > 0) return 1;
-  // Default: a chain-like walk (depth <= 2, e.g. Hörner) keeps few
-  // accumulators and gains from more points per lane (4 FP64, 2 otherwise);
-  // deeper walks spend those registers on the stack (2 FP64, 1 otherwise).
-  const bool shallow = t->depth <= 2;
-  int p = opts && opts->points_per_lane > 0 ? opts->points_per_lane
-          : t->domain == FPE_F64               ? (shallow ? 4 : 2)
-                                               : (shallow ? 2 : 1);
+  if (t->n_offtable > 0 || t->n_table > kTableCapMulti) return 1;
+  // Default: 4 points per lane for FP64, 2 otherwise (measured best on
+  // MI355X for both chain-like and deep walks once the power table lives in
+  // private memory); walks deeper than 8 hold twice the accumulators and take
+  // half as many points.
+  int p = opts && opts->points_per_lane > 0 ? opts->points_per_lane : (t->domain == FPE_F64 ? 4 : 2);
   if (t->depth > 8) p = std::min(p, t->domain == FPE_F64 ? 2 : 1);
   if (t->domain != FPE_F64) p = std::min(p, 2);
   return p >= 4 ? 4 : p >= 2 ? 2 : 1;
@@ -61,7 +48,6 @@ fpe_status launch_eval(const fpe_tree* t, const void* const* pts, int64_t npts, 
   L.offt = t->n_offtable > 0;
   L.nblocks = blocks_for(npts, L.ppl);
   L.stream = st;
-  L.lds = lds_bytes(t, t->domain) * L.ppl;
   hipEvent_t eb = opts ? (hipEvent_t)opts->ev_walk_begin : nullptr;
   hipEvent_t ee = opts ? (hipEvent_t)opts->ev_walk_end : nullptr;
   if (t->domain == FPE_F64) {
@@ -93,7 +79,6 @@ fpe_status launch_eval(const fpe_tree* t, const void* const* pts, int64_t npts, 
     KernelLaunch F = L;
     F.ppl = 1;
     F.nblocks = std::min<int64_t>(blocks_for(npts, 1), 4096);
-    F.lds = lds_bytes(t, kLdsFallback);
     launch_fallback(F, o.list, o.count, (double*)out);
     if (opts->nfallback_out) {
       hipError_t e = hipMemcpyAsync(opts->nfallback_out, o.count, sizeof(int64_t),

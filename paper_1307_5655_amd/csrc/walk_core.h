@@ -345,52 +345,38 @@ __device__ __forceinline__ void chain_dd(const DevTree& tr, const double* x, Emi
   else regs(h);
 }
 
-// LDS entries of a table: small tables (at most kTableCap entries) keep
-// entries 0..kRegPowers-1 only in registers and the rest in LDS; larger
-// tables run their chain in LDS and keep every entry there.
-__device__ __forceinline__ int lds_first(int n_table) { return n_table <= kTableCap ? kRegPowers : 0; }
-__host__ __device__ inline int lds_entries(int n_table) {
-  return n_table <= kTableCap ? (n_table > kRegPowers ? n_table - kRegPowers : 0) : n_table;
-}
+// Where the entries of a table live: entries 0..kRegPowers-1 (the most used
+// powers, ordered so by the compiler) are copied into registers; the whole
+// table lives in a per-lane private array (scratch memory, cached in L1/L2
+// and sized by the runtime for the resident waves) from which the rarely
+// used entries are read.  The table takes no LDS, so occupancy is set by
+// registers alone.  A table of at most kTableCap entries is built by the
+// register chain (chain_dd); a larger one runs its chain in the private
+// array.
 
 // Register copies of entries 0..3 (static indices) and the dynamic reader.
 template <class E>
 struct RegPow {
   E r[kRegPowers];
   template <class Get>
-  __device__ __forceinline__ E any(uint32_t i, Get&& lds) const {
+  __device__ __forceinline__ E any(uint32_t i, Get&& mem) const {
     switch (i) {
       case 0: return r[0];
       case 1: return r[1];
       case 2: return r[2];
       case 3: return r[3];
-      default: return lds(i);
+      default: return mem(i);
     }
   }
 };
 
+template <int CAP>
 struct TabF64 {
-  double* hi;          // LDS entries [lds_first..n_table) at [(i - first) * stride + col]
-  float* lo;           // only for tables above kTableCap entries (chain in LDS)
-  int col, stride, first;
-  RegPow<double> rp;
-  static constexpr size_t bytes_per_entry = kWave * sizeof(double);
-  static constexpr size_t bytes_per_entry_big = kWave * (sizeof(double) + sizeof(float));
-  __device__ __forceinline__ void bind(char* lds, int n_table, int j, int ppl) {
-    stride = ppl * kWave;
-    col = j * kWave + (threadIdx.x & (kWave - 1));
-    first = lds_first(n_table);
-    hi = (double*)lds;
-    lo = (float*)(lds + (size_t)lds_entries(n_table) * stride * sizeof(double));
-  }
-  __device__ __forceinline__ double& at(uint32_t i) const { return hi[(i - first) * stride + col]; }
-  __device__ __forceinline__ void build(const DevTree& tr, const double* x) {
-#pragma unroll
-    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = 0.0;
-    if (tr.n_table <= kTableCap) {
-      chain_dd(tr, x, [&](int i, const DD& v) {
-        if (i >= kRegPowers) at(i) = v.h;
-      }, [&](const double* h) {
+  double pm[CAP];         // entry i at pm[i] (private)
+  float pl[CAP];          // large tables: low word / high word during the chain
+  __device__ __forceinline__ void build(const DevTree& tr, const double* x, RegPow<double>& rp) {
+    if (CAP <= kTableCap || tr.n_table <= kTableCap) {
+      chain_dd(tr, x, [&](int i, const DD& v) { pm[i] = v.h; }, [&](const double* h) {
 #pragma unroll
         for (int k = 0; k < kRegPowers; ++k) rp.r[k] = h[k];
       });
@@ -401,114 +387,53 @@ struct TabF64 {
         if (st.kind == kChainLoad) {
           r = DD{coord(x, st.s1), 0.0};
         } else {
-          const double h1 = at(st.s1), h2 = at(st.s2);
-          r = dd_mul(DD{h1, h1 * (double)lo[st.s1 * stride + col]}, DD{h2, h2 * (double)lo[st.s2 * stride + col]});
+          const double h1 = pm[st.s1], h2 = pm[st.s2];
+          r = dd_mul(DD{h1, h1 * (double)pl[st.s1]}, DD{h2, h2 * (double)pl[st.s2]});
         }
-        at(st.dst) = r.h;
-        lo[st.dst * stride + col] = rel_lo(r);
+        pm[st.dst] = r.h;
+        pl[st.dst] = rel_lo(r);
       }
 #pragma unroll
-      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? at(k) : 0.0;
+      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = pm[k];
     }
   }
-  template <int I>
-  __device__ __forceinline__ double reg() const { return rp.r[I]; }
-  __device__ __forceinline__ double get(uint32_t i) const { return at(i); }
-  __device__ __forceinline__ double getany(uint32_t i) const {
-    return rp.any(i, [&](uint32_t k) { return at(k); });
-  }
+  __device__ __forceinline__ double get(uint32_t i) const { return pm[i]; }
 };
 
 // The fallback reads the powers as double-double (hi + lo).
+template <int CAP>
 struct TabDD {
-  double* hi;          // LDS entries, as TabF64
-  float* lo;           // low word / high word
-  int col, stride, first;
-  RegPow<DD> rp;
-  static constexpr size_t bytes_per_entry = kWave * (sizeof(double) + sizeof(float));
-  __device__ __forceinline__ void bind(char* lds, int n_table, int j, int ppl) {
-    stride = ppl * kWave;
-    col = j * kWave + (threadIdx.x & (kWave - 1));
-    first = lds_first(n_table);
-    hi = (double*)lds;
-    lo = (float*)(lds + (size_t)lds_entries(n_table) * stride * sizeof(double));
-  }
-  __device__ __forceinline__ DD at(uint32_t i) const {
-    const double h = hi[(i - first) * stride + col];
-    return DD{h, h * (double)lo[(i - first) * stride + col]};
-  }
-  __device__ __forceinline__ void put(uint32_t i, const DD& v) const {
-    hi[(i - first) * stride + col] = v.h;
-    lo[(i - first) * stride + col] = rel_lo(v);
-  }
-  __device__ __forceinline__ void build(const DevTree& tr, const double* x) {
-#pragma unroll
-    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = DD{0.0, 0.0};
-    if (tr.n_table <= kTableCap) {
-      chain_dd(tr, x, [&](int i, const DD& v) {
-        if (i >= kRegPowers) put(i, v);
-      }, [&](const double* h, const float* l) {
+  DD pm[CAP];             // entry i at pm[i] (private)
+  __device__ __forceinline__ void build(const DevTree& tr, const double* x, RegPow<DD>& rp) {
+    if (CAP <= kTableCap || tr.n_table <= kTableCap) {
+      chain_dd(tr, x, [&](int i, const DD& v) { pm[i] = v; }, [&](const double* h, const float* l) {
 #pragma unroll
         for (int k = 0; k < kRegPowers; ++k) rp.r[k] = DD{h[k], h[k] * (double)l[k]};
       });
     } else {
       for (int c = 0; c < tr.n_chain; ++c) {
         const ChainStep st = tr.chain[c];
-        put(st.dst, st.kind == kChainLoad ? DD{coord(x, st.s1), 0.0} : dd_mul(at(st.s1), at(st.s2)));
+        pm[st.dst] = st.kind == kChainLoad ? DD{coord(x, st.s1), 0.0} : dd_mul(pm[st.s1], pm[st.s2]);
       }
 #pragma unroll
-      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? at(k) : DD{0.0, 0.0};
+      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = pm[k];
     }
   }
-  template <int I>
-  __device__ __forceinline__ DD reg() const { return rp.r[I]; }
-  __device__ __forceinline__ DD get(uint32_t i) const { return at(i); }
-  __device__ __forceinline__ DD getany(uint32_t i) const {
-    return rp.any(i, [&](uint32_t k) { return at(k); });
-  }
+  __device__ __forceinline__ DD get(uint32_t i) const { return pm[i]; }
 };
 
+template <int CAP>
 struct TabM61 {
-  uint64_t* v;         // LDS entries, as TabF64
-  int col, stride, first;
-  RegPow<uint64_t> rp;
-  static constexpr size_t bytes_per_entry = kWave * sizeof(uint64_t);
-  __device__ __forceinline__ void bind(char* lds, int n_table, int j, int ppl) {
-    stride = ppl * kWave;
-    col = j * kWave + (threadIdx.x & (kWave - 1));
-    first = lds_first(n_table);
-    v = (uint64_t*)lds;
-  }
-  __device__ __forceinline__ uint64_t& at(uint32_t i) const { return v[(i - first) * stride + col]; }
-  __device__ __forceinline__ void build(const DevTree& tr, const uint64_t* x) {
-#pragma unroll
-    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = 0;
-    if (tr.n_table <= kTableCap) {
-      uint64_t t[kTableCap];
-#pragma unroll
-      for (int i = 0; i < kTableCap; ++i) t[i] = 0;
-      for (int c = 0; c < tr.n_chain; ++c) {
-        const ChainStep st = tr.chain[c];
-        t[st.dst] = st.kind == kChainLoad ? coord(x, st.s1) : m61_mul(t[st.s1], t[st.s2]);
-      }
-#pragma unroll
-      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = t[k];
-      for (int i = kRegPowers; i < tr.n_table; ++i) at(i) = t[i];
-    } else {
-      for (int c = 0; c < tr.n_chain; ++c) {
-        const ChainStep st = tr.chain[c];
-        at(st.dst) = st.kind == kChainLoad ? coord(x, st.s1) : m61_mul(at(st.s1), at(st.s2));
-      }
-#pragma unroll
-      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? at(k) : 0;
+  uint64_t pm[CAP];         // entry i at pm[i] (private)
+  __device__ __forceinline__ void build(const DevTree& tr, const uint64_t* x, RegPow<uint64_t>& rp) {
+    for (int c = 0; c < tr.n_chain; ++c) {
+      const ChainStep st = tr.chain[c];
+      pm[st.dst] = st.kind == kChainLoad ? coord(x, st.s1) : m61_mul(pm[st.s1], pm[st.s2]);
     }
+#pragma unroll
+    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? pm[k] : 0;
   }
-  template <int I>
-  __device__ __forceinline__ uint64_t reg() const { return rp.r[I]; }
-  __device__ __forceinline__ uint64_t get(uint32_t i) const { return at(i); }
-  __device__ __forceinline__ uint64_t getany(uint32_t i) const {
-    return rp.any(i, [&](uint32_t k) { return at(k); });
-  }
+  __device__ __forceinline__ uint64_t get(uint32_t i) const { return pm[i]; }
 };
 
 // Three-float powers for the double-float walk: the double-double value of
@@ -521,66 +446,43 @@ __device__ __forceinline__ P3 split3_dd(DD r) {
   return P3{h, m, l};
 }
 
+template <int CAP>
 struct TabP3 {
-  float* f;            // LDS entries at [(i - first)][3][stride]
-  int col, stride, first;
-  RegPow<P3> rp;
-  static constexpr size_t bytes_per_entry = kWave * 3 * sizeof(float);
-  __device__ __forceinline__ void bind(char* lds, int n_table, int j, int ppl) {
-    stride = ppl * kWave;
-    col = j * kWave + (threadIdx.x & (kWave - 1));
-    first = lds_first(n_table);
-    f = (float*)lds;
-  }
-  __device__ __forceinline__ P3 load(uint32_t i) const {
-    const float* p = f + (i - first) * (3 * stride) + col;
-    return P3{p[0], p[stride], p[2 * stride]};
-  }
-  __device__ __forceinline__ void store(uint32_t i, P3 v) const {
-    float* p = f + (i - first) * (3 * stride) + col;
-    p[0] = v.h;
-    p[stride] = v.m;
-    p[2 * stride] = v.l;
-  }
-  __device__ __forceinline__ void build(const DevTree& tr, const double* x) {
-#pragma unroll
-    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = P3{0.f, 0.f, 0.f};
-    if (tr.n_table <= kTableCap) {
-      chain_dd(tr, x, [&](int i, const DD& v) {
-        if (i >= kRegPowers) store(i, split3_dd(v));
-      }, [&](const double* h, const float* l) {
+  P3 pm[CAP];             // entry i at pm[i] (private)
+  __device__ __forceinline__ void build(const DevTree& tr, const double* x, RegPow<P3>& rp) {
+    if (CAP <= kTableCap || tr.n_table <= kTableCap) {
+      chain_dd(tr, x, [&](int i, const DD& v) { pm[i] = split3_dd(v); }, [&](const double* h, const float* l) {
 #pragma unroll
         for (int k = 0; k < kRegPowers; ++k) rp.r[k] = split3_dd(DD{h[k], h[k] * (double)l[k]});
       });
     } else {
-      // large table: the chain runs on the three-float values in LDS
+      // large table: the chain runs on the three-float values
       for (int c = 0; c < tr.n_chain; ++c) {
         const ChainStep st = tr.chain[c];
         if (st.kind == kChainLoad) {
-          store(st.dst, split3_dd(DD{coord(x, st.s1), 0.0}));
+          pm[st.dst] = split3_dd(DD{coord(x, st.s1), 0.0});
         } else {
-          const P3 a = load(st.s1), b = load(st.s2);
-          store(st.dst, split3_dd(dd_mul(DD{(double)a.h + (double)a.m, (double)a.l},
-                                         DD{(double)b.h + (double)b.m, (double)b.l})));
+          const P3 a = pm[st.s1], b = pm[st.s2];
+          pm[st.dst] = split3_dd(dd_mul(DD{(double)a.h + (double)a.m, (double)a.l},
+                                        DD{(double)b.h + (double)b.m, (double)b.l}));
         }
       }
 #pragma unroll
-      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? load(k) : P3{0.f, 0.f, 0.f};
+      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = pm[k];
     }
   }
-  template <int I>
-  __device__ __forceinline__ P3 reg() const { return rp.r[I]; }
-  __device__ __forceinline__ P3 get(uint32_t i) const { return load(i); }
-  __device__ __forceinline__ P3 getany(uint32_t i) const {
-    return rp.any(i, [&](uint32_t k) { return load(k); });
-  }
+  __device__ __forceinline__ P3 get(uint32_t i) const { return pm[i]; }
 };
 
-template <class Ar> struct TabFor;
-template <> struct TabFor<ArF64> { using T = TabF64; };
-template <> struct TabFor<ArDD> { using T = TabDD; };
-template <> struct TabFor<ArM61> { using T = TabM61; };
-template <> struct TabFor<ArDF32> { using T = TabP3; };
+// CAP: entries a table can hold; kernels with several points per lane only
+// take tables of at most kTableCapMulti entries (the launcher sends larger
+// ones to the one-point kernels), which keeps their private arrays small.
+template <class Ar, int CAP> struct TabFor;
+template <int CAP> struct TabFor<ArF64, CAP> { using T = TabF64<CAP>; };
+template <int CAP> struct TabFor<ArDD, CAP> { using T = TabDD<CAP>; };
+template <int CAP> struct TabFor<ArM61, CAP> { using T = TabM61<CAP>; };
+template <int CAP> struct TabFor<ArDF32, CAP> { using T = TabP3<CAP>; };
+template <int PPL> constexpr int table_cap() { return PPL > 1 ? kTableCapMulti : kMaxTable; }
 
 // ----------------------------------------------------------------------------
 // the walk
@@ -599,11 +501,12 @@ struct Walker {
   using Acc = typename Ar::Acc;
   using Pow = typename Ar::Pow;
   using In = typename Ar::In;
-  using Tab = typename TabFor<Ar>::T;
+  using Tab = typename TabFor<Ar, table_cap<PPL>()>::T;
 
   const Op* __restrict__ ops;
   const In (*x)[8];   // x[j][var]: the coordinates of point j (kernel locals)
-  Tab* tab;           // tab[j]: the power table of point j (kernel locals)
+  Tab* tab;           // tab[j]: the power table of point j (private memory)
+  RegPow<Pow> rp[PPL];   // rp[j]: entries 0..kRegPowers-1 of point j (registers)
   Acc m[DMAX][PPL];
   Acc y[PPL];
   In xv[OFFT ? PPL : 1][8];   // coordinates by value, for powers computed on the fly
@@ -638,19 +541,24 @@ struct Walker {
   template <uint32_t PC>
   __device__ __forceinline__ Pow power(const Op& o, int j) const {
     if constexpr (PC < (uint32_t)kRegPowers) {
-      return tab[j].template reg<(int)PC>();
+      return rp[j].r[PC];
     } else if constexpr (PC == kPowLds) {
       return tab[j].get(op_pidx(o.info));
     } else {
       const uint32_t p1 = op_pidx(o.info), p2 = op_pidx2(o.info);
       if (p2 != kNoPair) {
-        const Pow a = Ar::pair(tab[j].getany(p1), tab[j].getany(p2));
-        if (op_deg(o.deg) & kThirdBit) return Ar::pair(a, tab[j].getany(op_deg(o.deg) & 0xFFu));
+        const Pow a = Ar::pair(getany(j, p1), getany(j, p2));
+        if (op_deg(o.deg) & kThirdBit) return Ar::pair(a, getany(j, op_deg(o.deg) & 0xFFu));
         return a;
       }
       if constexpr (OFFT) return Ar::off_table(xvar(j, op_var(o.info)), o);
-      return tab[j].getany(p1);
+      return getany(j, p1);
     }
+  }
+
+  // entry i of point j's table, from registers or private memory
+  __device__ __forceinline__ Pow getany(int j, uint32_t i) const {
+    return rp[j].any(i, [&](uint32_t k) { return tab[j].get(k); });
   }
 
   // One op with dispatch code C: depth L (L accumulators open, the top is
@@ -695,12 +603,36 @@ struct Walker {
   // The walk: one flat loop over the ops and one switch on the op's dispatch
   // code (set by the host), whose cases carry compile-time accumulator
   // indices.
+  // Waits for the outstanding scalar load of the next op (s_waitcnt
+  // lgkmcnt(0); vmcnt and expcnt left at their maxima).  Scalar loads may
+  // return out of order, so without this wait at the end of every op the
+  // compiler would wait at the loop head, right after issuing the load.
+  static __device__ __forceinline__ void settle() { __builtin_amdgcn_s_waitcnt(0xC07F); }
+
+  // The next op's scalar load is issued before this op runs and settled
+  // after it, so its latency overlaps this op's dispatch and arithmetic (the
+  // op arrays end with one zero record after END, so the load past END stays
+  // in bounds).
   __device__ __forceinline__ void walk() {
-    const Op* __restrict__ op = ops;
+    // the op array is read-only while a kernel runs: reading it through the
+    // constant address space keeps its loads scalar whatever the kernel
+    // stores or waits on
+    using CW = const __attribute__((address_space(4))) uint64_t;
+    CW* __restrict__ op = (CW*)ops;
+    static_assert(sizeof(Op) == 4 * sizeof(uint64_t), "op records are 32 bytes");
+    auto fetch = [](CW* p) {
+      uint64_t w[4] = {p[0], p[1], p[2], p[3]};
+      Op r;
+      __builtin_memcpy(&r, w, sizeof r);
+      return r;
+    };
+    Op next = fetch(op);
+    settle();
 #pragma unroll 1
     for (;;) {
-      const Op o = *op;
-      ++op;
+      const Op o = next;
+      op += 4;
+      next = fetch(op);
       switch (op_code(o.deg)) {
 #define FPE_END(c) \
   case c: finish<((c) >> 6)>(o); return;
@@ -730,6 +662,7 @@ struct Walker {
         default:
           break;
       }
+      settle();
     }
   }
 #undef FPE_FOR_J
@@ -737,7 +670,7 @@ struct Walker {
   __device__ __forceinline__ void run(const DevTree& tr) {
     ops = Ar::ops(tr);
 #pragma unroll
-    for (int j = 0; j < PPL; ++j) tab[j].build(tr, x[j]);
+    for (int j = 0; j < PPL; ++j) tab[j].build(tr, x[j], rp[j]);
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {
 #pragma unroll
@@ -747,13 +680,11 @@ struct Walker {
   }
 };
 
-// Evaluate PPL points of this lane (their columns of the LDS power table).
+// Evaluate PPL points of this lane (one power table each).
 template <class Ar, int DMAX, int PPL, bool OFFT>
-__device__ __forceinline__ void walk_points(const DevTree& tr, const typename Ar::In (*x)[8], char* lds,
+__device__ __forceinline__ void walk_points(const DevTree& tr, const typename Ar::In (*x)[8],
                                             typename Ar::Acc* y) {
-  typename TabFor<Ar>::T tab[PPL];
-#pragma unroll
-  for (int j = 0; j < PPL; ++j) tab[j].bind(lds, tr.n_table, j, PPL);
+  typename TabFor<Ar, table_cap<PPL>()>::T tab[PPL];
   Walker<Ar, DMAX, PPL, OFFT> w(x, tab);
   w.run(tr);
 #pragma unroll
@@ -761,13 +692,12 @@ __device__ __forceinline__ void walk_points(const DevTree& tr, const typename Ar
 }
 
 template <class Ar, int DMAX, bool OFFT>
-__device__ __forceinline__ typename Ar::Acc walk_point(const DevTree& tr, const typename Ar::In* x,
-                                                       char* lds) {
+__device__ __forceinline__ typename Ar::Acc walk_point(const DevTree& tr, const typename Ar::In* x) {
   typename Ar::In xx[1][8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) xx[0][v] = x[v];
   typename Ar::Acc y[1];
-  walk_points<Ar, DMAX, 1, OFFT>(tr, xx, lds, y);
+  walk_points<Ar, DMAX, 1, OFFT>(tr, xx, y);
   return y[0];
 }
 
