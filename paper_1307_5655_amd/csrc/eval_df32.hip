@@ -36,22 +36,31 @@ __global__ __launch_bounds__(kBlock) void k_eval_df32(DevTree tr, Pts<double> P,
   }
 }
 
-// FP64 fallback: double-double walk over the flagged points.  The grid is
-// fixed; wavefronts stride over the count read from device memory.
-template <int DMAX, bool OFFT>
+// FP64 fallback: double-double walk over the flagged points, PPL of them per
+// lane.  The grid is fixed; wavefronts stride over the count read from
+// device memory.
+template <int DMAX, int PPL, bool OFFT>
 __global__ __launch_bounds__(kBlock) void k_fallback_dd(DevTree tr, Pts<double> P,
                                                         const int32_t* __restrict__ list,
                                                         const int64_t* __restrict__ count,
                                                         double* __restrict__ out) {
   const int64_t n = *count;
-  for (int64_t base = (int64_t)blockIdx.x * kBlock; base < n; base += (int64_t)gridDim.x * kBlock) {
-    const int64_t k = base + threadIdx.x;
-    double x[8];
-    const int64_t i = k < n ? list[k] : -1;
+  const int64_t stride = (int64_t)gridDim.x * kBlock * PPL;
+  for (int64_t base = (int64_t)blockIdx.x * kBlock * PPL; base < n; base += stride) {
+    double x[PPL][8];
+    int64_t idx[PPL];
 #pragma unroll
-    for (int v = 0; v < 8; ++v) x[v] = (i >= 0 && v < tr.nvars) ? P.p[v][i] : 0.0;
-    const DD r = walk_point<ArDD, DMAX, OFFT>(tr, x);
-    if (i >= 0) out[i] = r.h + r.l;
+    for (int j = 0; j < PPL; ++j) {
+      const int64_t k = base + (int64_t)j * kWave + threadIdx.x;
+      idx[j] = k < n ? list[k] : -1;
+#pragma unroll
+      for (int v = 0; v < 8; ++v) x[j][v] = (idx[j] >= 0 && v < tr.nvars) ? P.p[v][idx[j]] : 0.0;
+    }
+    DD r[PPL];
+    walk_points<ArDD, DMAX, PPL, OFFT>(tr, x, r);
+#pragma unroll
+    for (int j = 0; j < PPL; ++j)
+      if (idx[j] >= 0) out[idx[j]] = r[j].h + r[j].l;
   }
 }
 
@@ -74,20 +83,22 @@ void launch_df32(const KernelLaunch& L, const F32COut& o) {
   }
 }
 
-template <int DMAX, bool OFFT>
+template <int DMAX, int PPL, bool OFFT>
 static void gofb(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out) {
   Pts<double> P{};
   for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const double*)L.pts[j];
-  hipLaunchKernelGGL((k_fallback_dd<DMAX, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), 0,
+  hipLaunchKernelGGL((k_fallback_dd<DMAX, PPL, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), 0,
                      L.stream, L.tr, P, list, count, out);
 }
 
 void launch_fallback(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out) {
   const bool d8 = L.tr.depth <= 8;
   if (L.offt) {
-    if (d8) gofb<8, true>(L, list, count, out); else gofb<kMaxDepth, true>(L, list, count, out);
+    if (d8) gofb<8, 1, true>(L, list, count, out); else gofb<kMaxDepth, 1, true>(L, list, count, out);
+  } else if (L.ppl >= 2 && d8) {
+    gofb<8, 2, false>(L, list, count, out);
   } else {
-    if (d8) gofb<8, false>(L, list, count, out); else gofb<kMaxDepth, false>(L, list, count, out);
+    if (d8) gofb<8, 1, false>(L, list, count, out); else gofb<kMaxDepth, 1, false>(L, list, count, out);
   }
 }
 

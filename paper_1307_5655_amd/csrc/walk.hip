@@ -76,9 +76,10 @@ fpe_status launch_eval(const fpe_tree* t, const void* const* pts, int64_t npts, 
     if (eb) (void)hipEventRecord(eb, st);
     launch_df32(L, o);
     if (ee) (void)hipEventRecord(ee, st);
+    // the fallback grid is fixed (the count is on the device): enough
+    // wavefronts to fill the chip at its occupancy, fewer for small inputs
     KernelLaunch F = L;
-    F.ppl = 1;
-    F.nblocks = std::min<int64_t>(blocks_for(npts, 1), 4096);
+    F.nblocks = std::min<int64_t>(blocks_for(npts, F.ppl), 8192);
     launch_fallback(F, o.list, o.count, (double*)out);
     if (opts->nfallback_out) {
       hipError_t e = hipMemcpyAsync(opts->nfallback_out, o.count, sizeof(int64_t),

@@ -221,6 +221,9 @@ constexpr float kU2 = 3.5527136788005009e-15f;   // 2^-48
 constexpr float kK1 = 20.0f * kU2;
 constexpr float kK2 = 6.0f * kU2;
 
+// EA / EB: whether a / b carry an inherited error bound (accumulators do;
+// the coefficients of a node are exact, so their terms are left out).
+template <bool EA, bool EB>
 __device__ __forceinline__ DF df_step(float ah, float al, float ea, float ta, const P3& X,
                                       float bh, float bl, float eb, float tb) {
   float p = ah * X.h;
@@ -235,7 +238,11 @@ __device__ __forceinline__ DF df_step(float ah, float al, float ea, float ta, co
   float hi = s + se;
   float lo = se - (hi - s);
   float ax = __builtin_fabsf(X.h) * 1.0000001f;
-  float e = __builtin_fmaf(ea, ax, eb);
+  float e;
+  if constexpr (EA && EB) e = __builtin_fmaf(ea, ax, eb);
+  else if constexpr (EA) e = ea * ax;
+  else if constexpr (EB) e = eb;
+  else e = 0.f;
   e = __builtin_fmaf(kK1, __builtin_fabsf(p), e);
   e = __builtin_fmaf(kK2, __builtin_fabsf(bh), e);
   float t = __builtin_fmaf(ta, ax, tb);
@@ -249,20 +256,20 @@ struct ArDF32 {
   using In = double;
   static __device__ __forceinline__ const Op* ops(const DevTree& t) { return t.ops32; }
   static __device__ __forceinline__ Acc fma_ca(const Op& o, const Pow& X, const Acc& top) {
-    return df_step(o.ah, o.al, 0.f, o.aabs, X, top.h, top.l, top.e, top.t);
+    return df_step<false, true>(o.ah, o.al, 0.f, o.aabs, X, top.h, top.l, top.e, top.t);
   }
   static __device__ __forceinline__ Acc fma_tb(const Acc& top, const Pow& X, const Op& o) {
-    return df_step(top.h, top.l, top.e, top.t, X, o.bh, o.bl, 0.f, o.babs);
+    return df_step<true, false>(top.h, top.l, top.e, top.t, X, o.bh, o.bl, 0.f, o.babs);
   }
   static __device__ __forceinline__ Acc fma_ab(const Op& o, const Pow& X) {
-    return df_step(o.ah, o.al, 0.f, o.aabs, X, o.bh, o.bl, 0.f, o.babs);
+    return df_step<false, false>(o.ah, o.al, 0.f, o.aabs, X, o.bh, o.bl, 0.f, o.babs);
   }
   static __device__ __forceinline__ Acc fma_tt(const Acc& top, const Pow& X, const Acc& below) {
-    return df_step(top.h, top.l, top.e, top.t, X, below.h, below.l, below.e, below.t);
+    return df_step<true, true>(top.h, top.l, top.e, top.t, X, below.h, below.l, below.e, below.t);
   }
   static __device__ __forceinline__ Acc leaf_root(const Op& o) { return DF{o.ah, o.al, 0.f, o.aabs}; }
   static __device__ __forceinline__ Acc mul(const Acc& a, const Pow& X) {
-    return df_step(a.h, a.l, a.e, a.t, X, 0.f, 0.f, 0.f, 0.f);
+    return df_step<true, false>(a.h, a.l, a.e, a.t, X, 0.f, 0.f, 0.f, 0.f);
   }
   static __device__ __forceinline__ Pow off_table(In xv, const Op& o) {
     // binary exponentiation in double-double, split into three floats
