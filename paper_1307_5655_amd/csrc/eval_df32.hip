@@ -73,9 +73,11 @@ static void go(const KernelLaunch& L, const F32COut& o) {
 }
 
 void launch_df32(const KernelLaunch& L, const F32COut& o) {
-  const bool d8 = L.tr.depth <= 8;
+  const bool d2 = L.tr.depth <= 2, d8 = L.tr.depth <= 8;
   if (L.offt) {
     if (d8) go<8, 1, true>(L, o); else go<kMaxDepth, 1, true>(L, o);
+  } else if (L.ppl >= 2 && d2) {
+    go<2, 2, false>(L, o);
   } else if (L.ppl >= 2 && d8) {
     go<8, 2, false>(L, o);
   } else {
@@ -92,9 +94,11 @@ static void gofb(const KernelLaunch& L, const int32_t* list, const int64_t* coun
 }
 
 void launch_fallback(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out) {
-  const bool d8 = L.tr.depth <= 8;
+  const bool d2 = L.tr.depth <= 2, d8 = L.tr.depth <= 8;
   if (L.offt) {
     if (d8) gofb<8, 1, true>(L, list, count, out); else gofb<kMaxDepth, 1, true>(L, list, count, out);
+  } else if (L.ppl >= 2 && d2) {
+    gofb<2, 2, false>(L, list, count, out);
   } else if (L.ppl >= 2 && d8) {
     gofb<8, 2, false>(L, list, count, out);
   } else {

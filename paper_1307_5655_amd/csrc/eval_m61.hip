@@ -27,9 +27,11 @@ static void go(const KernelLaunch& L, uint64_t* out) {
 }
 
 void launch_m61(const KernelLaunch& L, uint64_t* out) {
-  const bool d8 = L.tr.depth <= 8;
+  const bool d2 = L.tr.depth <= 2, d8 = L.tr.depth <= 8;
   if (L.offt) {
     if (d8) go<8, 1, true>(L, out); else go<kMaxDepth, 1, true>(L, out);
+  } else if (L.ppl >= 2 && d2) {
+    go<2, 2, false>(L, out);
   } else if (L.ppl >= 2 && d8) {
     go<8, 2, false>(L, out);
   } else {

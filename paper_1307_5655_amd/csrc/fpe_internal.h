@@ -174,9 +174,9 @@ size_t eval_workspace_bytes(const fpe_tree* t, int64_t npts);
 fpe_status launch_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out,
                           void* ws, size_t ws_bytes, void* stream);
 size_t compose_workspace_bytes(const fpe_tree* t, int32_t dq);
-constexpr int kMaxDepth = 16;   // stack depth the kernels hold (4 bits of the code)
+constexpr int kMaxDepth = 15;   // stack depth the kernels hold (the code's 4-bit level field)
 constexpr int kMaxTable = 48;   // power-table entries held per point (composition)
-constexpr int kTableCap = 16;   // tables up to this size are built by the register chain
+constexpr int kTableCap = 16;   // smallest table size the compiler tries
 constexpr int kTableCapMulti = 32;   // largest table of the kernels with several points per lane
 constexpr int kMaxServe = 256;  // requests per fused launch
 constexpr int kServeGrid = 4096;   // fixed grid of the fused kernels (workgroups)

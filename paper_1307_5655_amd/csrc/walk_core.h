@@ -318,48 +318,13 @@ __device__ __forceinline__ float rel_lo(const DD& r) {
   return (r.h != 0.0 && isfinite(r.h)) ? (float)(r.l / r.h) : 0.f;
 }
 
-// The power chain of one point in double-double, in registers (at most
-// kTableCap entries; the low word kept relative to the high word as a float:
-// about 77 bits).  emit(i, value) receives every entry; regs(h, l) receives
-// the register arrays (entries 0..kRegPowers-1 read with static indices).
-template <class Emit, class Regs>
-__device__ __forceinline__ void chain_dd(const DevTree& tr, const double* x, Emit&& emit, Regs&& regs) {
-  double h[kTableCap];
-  float l[kTableCap];
-#pragma unroll
-  for (int i = 0; i < kTableCap; ++i) {
-    h[i] = 0.0;
-    l[i] = 0.f;
-  }
-  for (int c = 0; c < tr.n_chain; ++c) {
-    const ChainStep st = tr.chain[c];
-    double hh;
-    float ll;
-    if (st.kind == kChainLoad) {
-      hh = coord(x, st.s1);
-      ll = 0.f;
-    } else {
-      const double h1 = h[st.s1], h2 = h[st.s2];
-      const DD r = dd_mul(DD{h1, h1 * (double)l[st.s1]}, DD{h2, h2 * (double)l[st.s2]});
-      hh = r.h;
-      ll = rel_lo(r);
-    }
-    h[st.dst] = hh;
-    l[st.dst] = ll;
-  }
-  for (int i = kRegPowers; i < tr.n_table; ++i) emit(i, DD{h[i], h[i] * (double)l[i]});
-  if constexpr (std::is_invocable_v<Regs, const double*, const float*>) regs(h, l);
-  else regs(h);
-}
-
-// Where the entries of a table live: entries 0..kRegPowers-1 (the most used
-// powers, ordered so by the compiler) are copied into registers; the whole
-// table lives in a per-lane private array (scratch memory, cached in L1/L2
-// and sized by the runtime for the resident waves) from which the rarely
-// used entries are read.  The table takes no LDS, so occupancy is set by
-// registers alone.  A table of at most kTableCap entries is built by the
-// register chain (chain_dd); a larger one runs its chain in the private
-// array.
+// Where the entries of a table live: the whole table lives in a per-lane
+// private array (scratch memory, cached in L1/L2 and sized by the runtime
+// for the resident waves), where the power chain runs once per point and
+// from which the rarely used entries are read; entries 0..kRegPowers-1 (the
+// most used powers, ordered so by the compiler) are copied into registers
+// for the walk.  The table takes no LDS and no registers beyond those
+// copies, so occupancy is set by the walk's accumulators.
 
 // Register copies of entries 0..3 (static indices) and the dynamic reader.
 template <class E>
@@ -380,29 +345,22 @@ struct RegPow {
 template <int CAP>
 struct TabF64 {
   double pm[CAP];         // entry i at pm[i] (private)
-  float pl[CAP];          // large tables: low word / high word during the chain
+  float pl[CAP];          // low word / high word, for the chain
   __device__ __forceinline__ void build(const DevTree& tr, const double* x, RegPow<double>& rp) {
-    if (CAP <= kTableCap || tr.n_table <= kTableCap) {
-      chain_dd(tr, x, [&](int i, const DD& v) { pm[i] = v.h; }, [&](const double* h) {
-#pragma unroll
-        for (int k = 0; k < kRegPowers; ++k) rp.r[k] = h[k];
-      });
-    } else {
-      for (int c = 0; c < tr.n_chain; ++c) {
-        const ChainStep st = tr.chain[c];
-        DD r;
-        if (st.kind == kChainLoad) {
-          r = DD{coord(x, st.s1), 0.0};
-        } else {
-          const double h1 = pm[st.s1], h2 = pm[st.s2];
-          r = dd_mul(DD{h1, h1 * (double)pl[st.s1]}, DD{h2, h2 * (double)pl[st.s2]});
-        }
-        pm[st.dst] = r.h;
-        pl[st.dst] = rel_lo(r);
+    for (int c = 0; c < tr.n_chain; ++c) {
+      const ChainStep st = tr.chain[c];
+      DD r;
+      if (st.kind == kChainLoad) {
+        r = DD{coord(x, st.s1), 0.0};
+      } else {
+        const double h1 = pm[st.s1], h2 = pm[st.s2];
+        r = dd_mul(DD{h1, h1 * (double)pl[st.s1]}, DD{h2, h2 * (double)pl[st.s2]});
       }
-#pragma unroll
-      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = pm[k];
+      pm[st.dst] = r.h;
+      pl[st.dst] = rel_lo(r);
     }
+#pragma unroll
+    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? pm[k] : 0.0;
   }
   __device__ __forceinline__ double get(uint32_t i) const { return pm[i]; }
 };
@@ -412,19 +370,12 @@ template <int CAP>
 struct TabDD {
   DD pm[CAP];             // entry i at pm[i] (private)
   __device__ __forceinline__ void build(const DevTree& tr, const double* x, RegPow<DD>& rp) {
-    if (CAP <= kTableCap || tr.n_table <= kTableCap) {
-      chain_dd(tr, x, [&](int i, const DD& v) { pm[i] = v; }, [&](const double* h, const float* l) {
-#pragma unroll
-        for (int k = 0; k < kRegPowers; ++k) rp.r[k] = DD{h[k], h[k] * (double)l[k]};
-      });
-    } else {
-      for (int c = 0; c < tr.n_chain; ++c) {
-        const ChainStep st = tr.chain[c];
-        pm[st.dst] = st.kind == kChainLoad ? DD{coord(x, st.s1), 0.0} : dd_mul(pm[st.s1], pm[st.s2]);
-      }
-#pragma unroll
-      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = pm[k];
+    for (int c = 0; c < tr.n_chain; ++c) {
+      const ChainStep st = tr.chain[c];
+      pm[st.dst] = st.kind == kChainLoad ? DD{coord(x, st.s1), 0.0} : dd_mul(pm[st.s1], pm[st.s2]);
     }
+#pragma unroll
+    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? pm[k] : DD{0.0, 0.0};
   }
   __device__ __forceinline__ DD get(uint32_t i) const { return pm[i]; }
 };
@@ -457,26 +408,20 @@ template <int CAP>
 struct TabP3 {
   P3 pm[CAP];             // entry i at pm[i] (private)
   __device__ __forceinline__ void build(const DevTree& tr, const double* x, RegPow<P3>& rp) {
-    if (CAP <= kTableCap || tr.n_table <= kTableCap) {
-      chain_dd(tr, x, [&](int i, const DD& v) { pm[i] = split3_dd(v); }, [&](const double* h, const float* l) {
-#pragma unroll
-        for (int k = 0; k < kRegPowers; ++k) rp.r[k] = split3_dd(DD{h[k], h[k] * (double)l[k]});
-      });
-    } else {
-      // large table: the chain runs on the three-float values
-      for (int c = 0; c < tr.n_chain; ++c) {
-        const ChainStep st = tr.chain[c];
-        if (st.kind == kChainLoad) {
-          pm[st.dst] = split3_dd(DD{coord(x, st.s1), 0.0});
-        } else {
-          const P3 a = pm[st.s1], b = pm[st.s2];
-          pm[st.dst] = split3_dd(dd_mul(DD{(double)a.h + (double)a.m, (double)a.l},
-                                        DD{(double)b.h + (double)b.m, (double)b.l}));
-        }
+    // the chain runs on the three-float values (h + m is exact in FP64, so
+    // each product is a double-double one)
+    for (int c = 0; c < tr.n_chain; ++c) {
+      const ChainStep st = tr.chain[c];
+      if (st.kind == kChainLoad) {
+        pm[st.dst] = split3_dd(DD{coord(x, st.s1), 0.0});
+      } else {
+        const P3 a = pm[st.s1], b = pm[st.s2];
+        pm[st.dst] = split3_dd(dd_mul(DD{(double)a.h + (double)a.m, (double)a.l},
+                                      DD{(double)b.h + (double)b.m, (double)b.l}));
       }
-#pragma unroll
-      for (int k = 0; k < kRegPowers; ++k) rp.r[k] = pm[k];
     }
+#pragma unroll
+    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? pm[k] : P3{0.f, 0.f, 0.f};
   }
   __device__ __forceinline__ P3 get(uint32_t i) const { return pm[i]; }
 };
@@ -640,12 +585,22 @@ struct Walker {
       const Op o = next;
       op += 4;
       next = fetch(op);
+      if constexpr (DMAX <= 2) {
+        // chain-like walks (Hörner): almost every op is NODE_OPEN at depth 1
+        // with the first register power; test it before the switch
+        constexpr uint32_t kHot = make_code(1, kNodeOpen, 0);
+        if (op_code(o.deg) == kHot) {
+          step<kHot>(o);
+          settle();
+          continue;
+        }
+      }
       switch (op_code(o.deg)) {
 #define FPE_END(c) \
   case c: finish<((c) >> 6)>(o); return;
 #define FPE_OP(c)                                                          \
   case c:                                                                  \
-    if constexpr (((c) & 15) < (DMAX > 8 ? 16 : 8)) step<(c)>(o);          \
+    if constexpr (((c) & 15) <= DMAX) step<(c)>(o);                        \
     break;
 #define FPE_L(k, p)                                                        \
   FPE_OP(1 + 16 * (k) + 64 * (p)) FPE_OP(2 + 16 * (k) + 64 * (p))          \

@@ -59,6 +59,26 @@ def test_dense_1023_f64(dev, scheme):
     check_f64(y, inp.coeffs, inp.points)
 
 
+@pytest.mark.parametrize("log2n,depth", [(15, 8), (17, 9)])
+def test_deep_estrin_walks(dev, log2n, depth):
+    """Walks of depth 8 (the deepest the depth-8 kernels take, every level
+    used) and 9 (the deep kernels), in all three domains."""
+    n = 1 << log2n
+    say(f"estrin n=2^{log2n} walk depth {depth}")
+    inp = fpe_inputs.dense_uni(npts=4096 + 37, degree=n - 1, seed_k=1)
+    y, t = eval_uni(inp.coeffs, inp.points, "estrin", fpe.F64, dev)
+    assert t.info.walk_depth == depth
+    check_f64(y, inp.coeffs, inp.points)
+    y, t = eval_uni(inp.coeffs, inp.points, "estrin", fpe.F32C, dev)
+    check_f32c(y, inp.coeffs, inp.points)
+    m = fpe_inputs.random_modp_poly(1, n, n - 1, 1000 + 37, seed=(600 + log2n,))
+    t = fpe.Tree(m.exps, m.coeffs, "estrin", fpe.MODP, fpe.P61).upload(dev)
+    assert t.info.walk_depth == depth
+    got = fpe.evaluate(t, [to_dev(m.points[0].view(np.int64), dev)]).cpu().numpy().view(np.uint64)
+    want = native.modp_eval(m.exps, m.coeffs, fpe.P61, m.points)
+    assert np.array_equal(got, want)
+
+
 def test_dense_horner_bit_identical_to_fma_horner(dev):
     say("dense n=1023 horner bit-exact")
     inp = fpe_inputs.dense_uni(npts=5000)
