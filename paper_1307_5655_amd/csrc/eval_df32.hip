@@ -4,7 +4,9 @@
 
 namespace fpe {
 
-template <int DMAX, int PPL, bool OFFT>
+// COND: the condition numbers are written (o.cond); without it the walk's
+// condition sums are dead and the compiler drops them.
+template <int DMAX, int PPL, bool OFFT, bool COND>
 __global__ __launch_bounds__(kBlock) void k_eval_df32(DevTree tr, Pts<double> P, int64_t npts,
                                                       F32COut o) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -20,9 +22,9 @@ __global__ __launch_bounds__(kBlock) void k_eval_df32(DevTree tr, Pts<double> P,
     if (i < npts) {
       double y;
       float cond;
-      flag = df32_finish(r[j], o.tol, o.force, y, cond);
+      flag = df32_finish<COND>(r[j], o.tol, o.force, y, cond);
       o.out[i] = y;
-      if (o.cond) o.cond[i] = cond;
+      if constexpr (COND) o.cond[i] = cond;
     }
     if (o.flags) {
       const uint64_t ballot = __ballot(flag);
@@ -68,16 +70,22 @@ template <int DMAX, int PPL, bool OFFT>
 static void go(const KernelLaunch& L, const F32COut& o) {
   Pts<double> P{};
   for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const double*)L.pts[j];
-  hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), 0,
-                     L.stream, L.tr, P, L.npts, o);
+  if (o.cond)
+    hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT, true>), dim3((unsigned)L.nblocks), dim3(kBlock), 0,
+                       L.stream, L.tr, P, L.npts, o);
+  else
+    hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT, false>), dim3((unsigned)L.nblocks), dim3(kBlock), 0,
+                       L.stream, L.tr, P, L.npts, o);
 }
 
 void launch_df32(const KernelLaunch& L, const F32COut& o) {
-  const bool d2 = L.tr.depth <= 2, d8 = L.tr.depth <= 8;
+  const bool d2 = L.tr.depth <= 2, d6 = L.tr.depth <= 6, d8 = L.tr.depth <= 8;
   if (L.offt) {
     if (d8) go<8, 1, true>(L, o); else go<kMaxDepth, 1, true>(L, o);
   } else if (L.ppl >= 2 && d2) {
     go<2, 2, false>(L, o);
+  } else if (L.ppl >= 2 && d6) {
+    go<6, 2, false>(L, o);
   } else if (L.ppl >= 2 && d8) {
     go<8, 2, false>(L, o);
   } else {
@@ -94,11 +102,13 @@ static void gofb(const KernelLaunch& L, const int32_t* list, const int64_t* coun
 }
 
 void launch_fallback(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out) {
-  const bool d2 = L.tr.depth <= 2, d8 = L.tr.depth <= 8;
+  const bool d2 = L.tr.depth <= 2, d6 = L.tr.depth <= 6, d8 = L.tr.depth <= 8;
   if (L.offt) {
     if (d8) gofb<8, 1, true>(L, list, count, out); else gofb<kMaxDepth, 1, true>(L, list, count, out);
   } else if (L.ppl >= 2 && d2) {
     gofb<2, 2, false>(L, list, count, out);
+  } else if (L.ppl >= 2 && d6) {
+    gofb<6, 2, false>(L, list, count, out);
   } else if (L.ppl >= 2 && d8) {
     gofb<8, 2, false>(L, list, count, out);
   } else {

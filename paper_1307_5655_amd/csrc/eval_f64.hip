@@ -27,11 +27,13 @@ static void go(const KernelLaunch& L, double* out) {
 }
 
 void launch_f64(const KernelLaunch& L, double* out) {
-  const bool d2 = L.tr.depth <= 2, d8 = L.tr.depth <= 8;
+  const bool d2 = L.tr.depth <= 2, d6 = L.tr.depth <= 6, d8 = L.tr.depth <= 8;
   if (L.offt) {
     if (d8) go<8, 1, true>(L, out); else go<kMaxDepth, 1, true>(L, out);
   } else if (L.ppl >= 4 && d2) {
     go<2, 4, false>(L, out);
+  } else if (L.ppl >= 4 && d6) {
+    go<6, 4, false>(L, out);
   } else if (L.ppl >= 4 && d8) {
     go<8, 4, false>(L, out);
   } else if (L.ppl >= 2) {

@@ -698,12 +698,17 @@ struct F32COut {
   int32_t force;
 };
 
+// The result hi + lo in FP64 and whether it must be re-evaluated: the bound
+// does not certify tol relative accuracy, or a component is not finite.  The
+// decision does not use the condition sum, so it is the same whether or not
+// COND (the condition number p~(|x|) / |y| as output) is computed.
+template <bool COND>
 __device__ __forceinline__ bool df32_finish(const DF& r, double tol, int force, double& y, float& cond) {
   y = (double)r.h + (double)r.l;
   const double ay = fabs(y);
   const double bound = (double)r.e * 1.01;
-  const bool finite = isfinite(r.h) && isfinite(r.l) && isfinite(r.e) && isfinite(r.t);
-  cond = (float)((double)r.t / ay);
+  const bool finite = isfinite(r.h) && isfinite(r.l) && isfinite(r.e);
+  if constexpr (COND) cond = (float)((double)r.t / ay);
   bool flag = !finite || !(bound <= tol * ay) || ay < 1e-30;
   if (force == 1) flag = true;
   if (force == 2) flag = false;
