@@ -142,6 +142,23 @@ def test_f32c_cond_and_flags(dev):
     assert bits.sum() == nfb.item()
 
 
+@pytest.mark.parametrize("scheme", ["horner", "estrin", "balanced"])
+def test_f32c_same_results_with_and_without_cond(dev, scheme):
+    """The kernel without condition output drops the condition sums; its
+    results and fallback decisions must be the same bits."""
+    say(f"f32c with/without cond {scheme}")
+    inp = fpe_inputs.sparse_uni(3000, npts=20_000 + 11)
+    n = len(inp.points)
+    cond = torch.empty(n, dtype=torch.float32, device=dev)
+    f1 = torch.zeros((n + 31) // 32 + 2, dtype=torch.int32, device=dev)
+    f2 = torch.zeros_like(f1)
+    y1, _ = eval_uni(inp.coeffs, inp.points, scheme, fpe.F32C, dev, cond_out=cond, flags_out=f1)
+    y2, _ = eval_uni(inp.coeffs, inp.points, scheme, fpe.F32C, dev, flags_out=f2)
+    assert np.array_equal(y1.view(np.uint64), y2.view(np.uint64))
+    assert np.array_equal(f1.cpu().numpy(), f2.cpu().numpy())
+    check_f32c(y2, inp.coeffs, inp.points)
+
+
 def test_edge_cases_f64(dev):
     say("edge cases")
     # single term, constant, zero constant term (root with a power), x = 0, +-1
