@@ -75,6 +75,42 @@ class HipEvents:
         return float(ms.value)
 
 
+# The HBM traffic of the compensated walk comes from two profiler passes
+# (FETCH_SIZE, WRITE_SIZE) over this benchmark, scaled by what the same
+# counters read for a plain copy of known size; the summary records a hash of
+# the kernel sources it was taken with, and the figure is reported only while
+# the sources are unchanged.
+TRAFFIC_SUMMARY = os.path.join(ROOT, "profiles", "k_eval_df32_sparse_uni_1e7_traffic.md")
+KERNEL_SOURCES = ("walk_core.h", "eval_df32.hip", "fpe_internal.h")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1307_5655_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    try:
+        text = open(TRAFFIC_SUMMARY).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if line.startswith("- ") and ":" in line:
+            k, v = line[2:].split(":", 1)
+            vals[k.strip()] = v.strip().strip("`")
+    if vals.get("kernel source hash") != kernel_source_hash():
+        return None
+    try:
+        return float(vals["HBM bytes per launch (scaled)"])
+    except (KeyError, ValueError):
+        return None
+
+
 def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, load: float):
     """Poisson arrivals of uneven evaluate requests (compensated FP32 with FP64
     fallback) through the server: first all at once to find the saturation
@@ -193,6 +229,9 @@ def main():
     ap.add_argument("--cpu-points", type=int, default=600_000)
     ap.add_argument("--no-extra", action="store_true", help="skip the served, mod-p and composition phases")
     ap.add_argument("--served-requests", type=int, default=400)
+    ap.add_argument("--copy-probe", type=float, default=0,
+                    help="after the timed steps, copy a device buffer of this many bytes three times "
+                         "(calibrates the HBM byte counters of a profiler run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; the evaluation shards by "
@@ -274,6 +313,7 @@ def main():
     f64_keys = [k for k in keys if k[2] == "f64"]
     f64_fma = sum(term_evals[k] for k in f64_keys)
     f64_time = sum(walk_ms[k] for k in f64_keys) * 1e-3
+    traffic = measured_traffic()
     roofline = {
         "kernel": "k_eval_df32 (compensated FP32 walk), 6 launches per step",
         "bound": "alu",
@@ -281,7 +321,7 @@ def main():
         "peak": FP32_VALU_PEAK / 1e12,
         "unit": "TOP/s (FP32 VALU lane-ops)",
         "frac": (df_ops / df_time) / FP32_VALU_PEAK,
-        "traffic": None,
+        "traffic": traffic,
         "ops_per_term_eval": DF32_OPS_PER_TERM,
         "avg_launch_ms": df_time * 1e3 / len(df_keys),
     }
@@ -315,6 +355,16 @@ def main():
             acc[f"n{n}_{s}"] = {"f32c_max_rel_err": float(np.max(np.abs(y32 - ref) / np.abs(ref))),
                                 "f64_max_scaled_err": float(np.max(np.abs(y64 - ref) / pt))}
             fb[f"n{n}_{s}"] = nfb[(n, s)].item() / args.points
+
+    if args.copy_probe > 0:
+        nbytes = int(args.copy_probe) // 8 * 8
+        src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # free the main workload before the side phases
     del trees, outs, ws, xs

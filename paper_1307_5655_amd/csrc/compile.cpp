@@ -689,7 +689,7 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
       // dispatch code: depth, kind, power class (END: depth 0, kind 0)
       uint32_t pc = kPowOther;
       if (pidx2 == kNoPair && pidx < (uint32_t)kRegPowers) pc = pidx;
-      else if (pidx2 == kNoPair && pidx != kOffTable) pc = kPowLds;
+      else if (pidx2 == kNoPair && pidx != kOffTable) pc = kPowMem;
       const uint32_t kind = op_kind(info);
       const uint32_t lvl = (uint32_t)std::min(depth_before, 15);
       const uint32_t code = kind == kEnd ? make_code(0, 0, (info & kEndHasPow) ? pc : kPowOther)

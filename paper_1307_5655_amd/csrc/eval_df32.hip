@@ -9,12 +9,13 @@ namespace fpe {
 template <int DMAX, int PPL, bool OFFT, bool COND>
 __global__ __launch_bounds__(kBlock) void k_eval_df32(DevTree tr, Pts<double> P, int64_t npts,
                                                       F32COut o) {
+  extern __shared__ __align__(16) char lds[];
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t base = (int64_t)blockIdx.x * kBlock * PPL + threadIdx.x;
   double x[PPL][8];
   load_points<double, PPL>(P, tr.nvars, base, npts, x);
   DF r[PPL];
-  walk_points<ArDF32, DMAX, PPL, OFFT>(tr, x, r);
+  walk_points<ArDF32, DMAX, PPL, OFFT>(tr, x, lds, r);
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
     const int64_t i = base + (int64_t)j * kWave;
@@ -46,6 +47,7 @@ __global__ __launch_bounds__(kBlock) void k_fallback_dd(DevTree tr, Pts<double> 
                                                         const int32_t* __restrict__ list,
                                                         const int64_t* __restrict__ count,
                                                         double* __restrict__ out) {
+  extern __shared__ __align__(16) char lds[];
   const int64_t n = *count;
   const int64_t stride = (int64_t)gridDim.x * kBlock * PPL;
   for (int64_t base = (int64_t)blockIdx.x * kBlock * PPL; base < n; base += stride) {
@@ -59,7 +61,7 @@ __global__ __launch_bounds__(kBlock) void k_fallback_dd(DevTree tr, Pts<double> 
       for (int v = 0; v < 8; ++v) x[j][v] = (idx[j] >= 0 && v < tr.nvars) ? P.p[v][idx[j]] : 0.0;
     }
     DD r[PPL];
-    walk_points<ArDD, DMAX, PPL, OFFT>(tr, x, r);
+    walk_points<ArDD, DMAX, PPL, OFFT>(tr, x, lds, r);
 #pragma unroll
     for (int j = 0; j < PPL; ++j)
       if (idx[j] >= 0) out[idx[j]] = r[j].h + r[j].l;
@@ -71,11 +73,11 @@ static void go(const KernelLaunch& L, const F32COut& o) {
   Pts<double> P{};
   for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const double*)L.pts[j];
   if (o.cond)
-    hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT, true>), dim3((unsigned)L.nblocks), dim3(kBlock), 0,
-                       L.stream, L.tr, P, L.npts, o);
+    hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT, true>), dim3((unsigned)L.nblocks), dim3(kBlock),
+                       (walk_lds_bytes<ArDF32, DMAX, PPL>()), L.stream, L.tr, P, L.npts, o);
   else
-    hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT, false>), dim3((unsigned)L.nblocks), dim3(kBlock), 0,
-                       L.stream, L.tr, P, L.npts, o);
+    hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT, false>), dim3((unsigned)L.nblocks), dim3(kBlock),
+                       (walk_lds_bytes<ArDF32, DMAX, PPL>()), L.stream, L.tr, P, L.npts, o);
 }
 
 void launch_df32(const KernelLaunch& L, const F32COut& o) {
@@ -97,8 +99,8 @@ template <int DMAX, int PPL, bool OFFT>
 static void gofb(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out) {
   Pts<double> P{};
   for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const double*)L.pts[j];
-  hipLaunchKernelGGL((k_fallback_dd<DMAX, PPL, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), 0,
-                     L.stream, L.tr, P, list, count, out);
+  hipLaunchKernelGGL((k_fallback_dd<DMAX, PPL, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock),
+                     (walk_lds_bytes<ArDD, DMAX, PPL>()), L.stream, L.tr, P, list, count, out);
 }
 
 void launch_fallback(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out) {

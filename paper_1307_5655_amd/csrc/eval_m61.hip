@@ -6,11 +6,12 @@ namespace fpe {
 template <int DMAX, int PPL, bool OFFT>
 __global__ __launch_bounds__(kBlock) void k_eval_m61(DevTree tr, Pts<uint64_t> P, int64_t npts,
                                                      uint64_t* __restrict__ out) {
+  extern __shared__ __align__(16) char lds[];
   const int64_t base = (int64_t)blockIdx.x * kBlock * PPL + threadIdx.x;
   uint64_t x[PPL][8];
   load_points<uint64_t, PPL>(P, tr.nvars, base, npts, x);
   uint64_t y[PPL];
-  walk_points<ArM61, DMAX, PPL, OFFT>(tr, x, y);
+  walk_points<ArM61, DMAX, PPL, OFFT>(tr, x, lds, y);
 #pragma unroll
   for (int j = 0; j < PPL; ++j) {
     const int64_t i = base + (int64_t)j * kWave;
@@ -22,8 +23,8 @@ template <int DMAX, int PPL, bool OFFT>
 static void go(const KernelLaunch& L, uint64_t* out) {
   Pts<uint64_t> P{};
   for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const uint64_t*)L.pts[j];
-  hipLaunchKernelGGL((k_eval_m61<DMAX, PPL, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock), 0,
-                     L.stream, L.tr, P, L.npts, out);
+  hipLaunchKernelGGL((k_eval_m61<DMAX, PPL, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock),
+                     (walk_lds_bytes<ArM61, DMAX, PPL>()), L.stream, L.tr, P, L.npts, out);
 }
 
 void launch_m61(const KernelLaunch& L, uint64_t* out) {

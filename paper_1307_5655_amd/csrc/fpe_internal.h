@@ -55,11 +55,13 @@ __host__ __device__ inline uint32_t op_pidx2(uint32_t info) { return (info >> 25
 // The dispatch code of an op, in the top 12 bits of its deg field (the
 // partial degree itself, < 2^20, uses the low 20 bits): bits 0-3 the stack
 // depth L, bits 4-5 the kind (LEAF_ADD, NODE_OPEN, LEAF_OPEN, NODE_ADD),
-// bits 6-8 where its power comes from (0-3: register entry 0-3, 4: one LDS
-// entry, 5: a product of two entries or computed on the fly).  LEAF_ADD at
+// bits 6-8 where its power comes from (0-3: register entry 0-3, 4: one entry
+// of the LDS tier or of the private table, 5: a product of two or three
+// entries, or computed on the fly).  LEAF_ADD at
 // depth 0 cannot occur, so codes with L = 0 and kind 0 mark the root (END).
 constexpr int kRegPowers = 4;   // table entries kept in registers
-enum PowClass : uint32_t { kPowLds = 4, kPowOther = 5 };
+constexpr int kLdsPowers = 4;   // the next entries, kept in LDS (see walk_core.h)
+enum PowClass : uint32_t { kPowMem = 4, kPowOther = 5 };
 constexpr uint32_t make_code(uint32_t level, uint32_t kind, uint32_t pclass) {
   return (level & 15u) | (kind << 4) | (pclass << 6);
 }
@@ -184,9 +186,11 @@ constexpr int kServeGrid = 4096;   // fixed grid of the fused kernels (workgroup
 struct ServeKernels {
   const void* zero;       // k_serve_zero(WorkTable*)
   const void* walk8;      // k_serve_walk<8>(WorkTable*)
-  const void* walk16;     // k_serve_walk<16>(WorkTable*)
+  const void* walk16;     // k_serve_walk<kMaxDepth>(WorkTable*)
   const void* fallback8;  // k_serve_fallback<8>(WorkTable*)
   const void* fallback16;
+  size_t walk_lds;        // dynamic LDS of the walk kernels (the power tables' LDS tier)
+  size_t fallback_lds;    // and of the fallback kernels
 };
 ServeKernels serve_kernels();
 size_t work_table_bytes();

@@ -28,6 +28,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_walk(WorkTable* wt) {
   const WorkItem* items = table_items(wt);
   const int64_t* prefix = table_prefix(wt);
   int64_t* counters = table_counters(wt);
+  extern __shared__ __align__(16) char lds[];
   for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
     const int r = find_item(prefix, n, b);
     const WorkItem& it = items[r];
@@ -38,10 +39,10 @@ __global__ __launch_bounds__(kBlock) void k_serve_walk(WorkTable* wt) {
     for (int j = 0; j < 8; ++j) x[j] = (in && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
     bool flag = false;
     if (it.domain == FPE_F64) {
-      const double y = walk_point<ArF64, DMAX, true>(it.tree, x);
+      const double y = walk_point<ArF64, DMAX, true>(it.tree, x, lds);
       if (in) it.out[i] = y;
     } else {
-      const DF rr = walk_point<ArDF32, DMAX, true>(it.tree, x);
+      const DF rr = walk_point<ArDF32, DMAX, true>(it.tree, x, lds);
       if (in) {
         double y;
         float cond;
@@ -59,6 +60,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_fallback(WorkTable* wt) {
   const int n = wt->n_items;
   const WorkItem* items = table_items(wt);
   const int64_t* counters = table_counters(wt);
+  extern __shared__ __align__(16) char lds[];
   for (int r = 0; r < n; ++r) {
     const WorkItem& it = items[r];
     if (it.domain != FPE_F32C) continue;
@@ -69,7 +71,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_fallback(WorkTable* wt) {
       double x[8];
 #pragma unroll
       for (int j = 0; j < 8; ++j) x[j] = (i >= 0 && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
-      const DD rr = walk_point<ArDD, DMAX, true>(it.tree, x);
+      const DD rr = walk_point<ArDD, DMAX, true>(it.tree, x, lds);
       if (i >= 0) it.out[i] = rr.h + rr.l;
     }
   }
@@ -82,6 +84,9 @@ ServeKernels serve_kernels() {
   k.walk16 = (const void*)k_serve_walk<kMaxDepth>;
   k.fallback8 = (const void*)k_serve_fallback<8>;
   k.fallback16 = (const void*)k_serve_fallback<kMaxDepth>;
+  k.walk_lds = std::max({walk_lds_bytes<ArF64, kMaxDepth, 1>(), walk_lds_bytes<ArDF32, kMaxDepth, 1>(),
+                         walk_lds_bytes<ArF64, 8, 1>(), walk_lds_bytes<ArDF32, 8, 1>()});
+  k.fallback_lds = std::max(walk_lds_bytes<ArDD, 8, 1>(), walk_lds_bytes<ArDD, kMaxDepth, 1>());
   return k;
 }
 

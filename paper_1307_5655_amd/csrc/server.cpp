@@ -176,12 +176,13 @@ fpe_status build_slot(fpe_server* s, Slot& sl) {
     wp.func = (void*)(c == 0 ? K.walk8 : K.walk16);
     wp.gridDim = dim3(kServeGrid);
     wp.blockDim = dim3(64);
-    wp.sharedMemBytes = 0;
+    wp.sharedMemBytes = (unsigned)K.walk_lds;
     wp.kernelParams = sl.args[c];
     if (hipGraphAddKernelNode(&w, sl.graph, &z, 1, &wp) != hipSuccess)
       return fail(FPE_EDEVICE, "server: graph kernel node failed");
     hipKernelNodeParams fp = wp;
     fp.func = (void*)(c == 0 ? K.fallback8 : K.fallback16);
+    fp.sharedMemBytes = (unsigned)K.fallback_lds;
     fp.gridDim = dim3(kServeGrid / 4);
     if (hipGraphAddKernelNode(&f, sl.graph, &w, 1, &fp) != hipSuccess)
       return fail(FPE_EDEVICE, "server: graph kernel node failed");

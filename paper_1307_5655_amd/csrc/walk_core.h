@@ -426,6 +426,50 @@ struct TabP3 {
   __device__ __forceinline__ P3 get(uint32_t i) const { return pm[i]; }
 };
 
+// LDS tier of the tables: entries kRegPowers .. kRegPowers+kLdsPowers-1 (the
+// next most used after the register copies) of every point of a wavefront,
+// stored as 32-bit planes [entry][word][point j][lane] so a wavefront reads 64
+// consecutive words (no bank conflicts).  One wavefront per workgroup, so a
+// workgroup's dynamic LDS is walk_lds_bytes<Ar, PPL>(): 6 KB for the
+// double-float walk at two points per lane.  Entries beyond the tier stay in
+// private memory; the tier keeps the table's hot part out of it, whose
+// working set is far beyond the caches at full occupancy.
+template <class E, int PPL>
+struct LdsTier {
+  static constexpr int kWords = (int)(sizeof(E) / 4);
+  static constexpr int kStride = PPL * kWave;
+  uint32_t* base;   // the workgroup's dynamic LDS
+  int col;          // j * 64 + lane is added per access
+  __device__ __forceinline__ uint32_t* at(uint32_t i, int w, int j) const {
+    return base + ((i - kRegPowers) * kWords + w) * kStride + j * kWave + col;
+  }
+  __device__ __forceinline__ void put(uint32_t i, int j, const E& v) const {
+    uint32_t u[kWords];
+    __builtin_memcpy(u, &v, sizeof v);
+#pragma unroll
+    for (int w = 0; w < kWords; ++w) *at(i, w, j) = u[w];
+  }
+  __device__ __forceinline__ E get(uint32_t i, int j) const {
+    uint32_t u[kWords];
+#pragma unroll
+    for (int w = 0; w < kWords; ++w) u[w] = *at(i, w, j);
+    E v;
+    __builtin_memcpy(&v, u, sizeof v);
+    return v;
+  }
+};
+// Whether a kernel uses the tier: not for chain-like walks (depth <= 2, whose
+// few powers all sit in registers), and not for the FP64 depth-6 kernel, whose
+// occupancy the tier's addressing would lower by one wave (measured slower).
+template <class Ar, int DMAX>
+constexpr bool lds_tier() {
+  return DMAX > 2 && !(std::is_same_v<Ar, ArF64> && DMAX == 6);
+}
+template <class Ar, int DMAX, int PPL>
+constexpr size_t walk_lds_bytes() {
+  return lds_tier<Ar, DMAX>() ? (size_t)kLdsPowers * sizeof(typename Ar::Pow) * PPL * kWave : 0;
+}
+
 // CAP: entries a table can hold; kernels with several points per lane only
 // take tables of at most kTableCapMulti entries (the launcher sends larger
 // ones to the one-point kernels), which keeps their private arrays small.
@@ -459,6 +503,7 @@ struct Walker {
   const In (*x)[8];   // x[j][var]: the coordinates of point j (kernel locals)
   Tab* tab;           // tab[j]: the power table of point j (private memory)
   RegPow<Pow> rp[PPL];   // rp[j]: entries 0..kRegPowers-1 of point j (registers)
+  LdsTier<Pow, PPL> lt;  // entries kRegPowers.. of the LDS tier
   Acc m[DMAX][PPL];
   Acc y[PPL];
   In xv[OFFT ? PPL : 1][8];   // coordinates by value, for powers computed on the fly
@@ -477,7 +522,9 @@ struct Walker {
     }
   }
 
-  __device__ __forceinline__ Walker(const In (*x_)[8], Tab* t_) : ops(nullptr), x(x_), tab(t_) {
+  __device__ __forceinline__ Walker(const In (*x_)[8], Tab* t_, char* lds) : ops(nullptr), x(x_), tab(t_) {
+    lt.base = (uint32_t*)lds;
+    lt.col = (int)(threadIdx.x & (kWave - 1));
     if constexpr (OFFT) {
 #pragma unroll
       for (int j = 0; j < PPL; ++j) {
@@ -494,8 +541,8 @@ struct Walker {
   __device__ __forceinline__ Pow power(const Op& o, int j) const {
     if constexpr (PC < (uint32_t)kRegPowers) {
       return rp[j].r[PC];
-    } else if constexpr (PC == kPowLds) {
-      return tab[j].get(op_pidx(o.info));
+    } else if constexpr (PC == kPowMem) {
+      return mem(j, op_pidx(o.info));
     } else {
       const uint32_t p1 = op_pidx(o.info), p2 = op_pidx2(o.info);
       if (p2 != kNoPair) {
@@ -508,9 +555,15 @@ struct Walker {
     }
   }
 
-  // entry i of point j's table, from registers or private memory
+  // entry i >= kRegPowers of point j's table: the LDS tier or private memory
+  __device__ __forceinline__ Pow mem(int j, uint32_t i) const {
+    if constexpr (lds_tier<Ar, DMAX>())
+      if (i < (uint32_t)(kRegPowers + kLdsPowers)) return lt.get(i, j);
+    return tab[j].get(i);
+  }
+  // entry i of point j's table, wherever it lives
   __device__ __forceinline__ Pow getany(int j, uint32_t i) const {
-    return rp[j].any(i, [&](uint32_t k) { return tab[j].get(k); });
+    return rp[j].any(i, [&](uint32_t k) { return mem(j, k); });
   }
 
   // One op with dispatch code C: depth L (L accumulators open, the top is
@@ -632,7 +685,11 @@ struct Walker {
   __device__ __forceinline__ void run(const DevTree& tr) {
     ops = Ar::ops(tr);
 #pragma unroll
-    for (int j = 0; j < PPL; ++j) tab[j].build(tr, x[j], rp[j]);
+    for (int j = 0; j < PPL; ++j) {
+      tab[j].build(tr, x[j], rp[j]);
+      if constexpr (lds_tier<Ar, DMAX>())
+        for (int i = kRegPowers; i < kRegPowers + kLdsPowers && i < tr.n_table; ++i) lt.put(i, j, tab[j].get(i));
+    }
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {
 #pragma unroll
@@ -644,22 +701,22 @@ struct Walker {
 
 // Evaluate PPL points of this lane (one power table each).
 template <class Ar, int DMAX, int PPL, bool OFFT>
-__device__ __forceinline__ void walk_points(const DevTree& tr, const typename Ar::In (*x)[8],
+__device__ __forceinline__ void walk_points(const DevTree& tr, const typename Ar::In (*x)[8], char* lds,
                                             typename Ar::Acc* y) {
   typename TabFor<Ar, table_cap<PPL>()>::T tab[PPL];
-  Walker<Ar, DMAX, PPL, OFFT> w(x, tab);
+  Walker<Ar, DMAX, PPL, OFFT> w(x, tab, lds);
   w.run(tr);
 #pragma unroll
   for (int j = 0; j < PPL; ++j) y[j] = w.y[j];
 }
 
 template <class Ar, int DMAX, bool OFFT>
-__device__ __forceinline__ typename Ar::Acc walk_point(const DevTree& tr, const typename Ar::In* x) {
+__device__ __forceinline__ typename Ar::Acc walk_point(const DevTree& tr, const typename Ar::In* x, char* lds) {
   typename Ar::In xx[1][8];
 #pragma unroll
   for (int v = 0; v < 8; ++v) xx[0][v] = x[v];
   typename Ar::Acc y[1];
-  walk_points<Ar, DMAX, 1, OFFT>(tr, xx, y);
+  walk_points<Ar, DMAX, 1, OFFT>(tr, xx, lds, y);
   return y[0];
 }
 
