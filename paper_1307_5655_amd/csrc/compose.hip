@@ -5,10 +5,13 @@
 //
 // The walk is the same stack program as the pointwise kernels, with
 // polynomial-valued accumulators: a step a * X + b becomes a polynomial
-// product with a power q^d of q plus a constant.  One workgroup walks one
-// instance; polynomials live in a per-instance workspace in HBM and every
-// product is split over the workgroup by output coefficient.  The powers
-// q^d are computed by the tree's power chain (q^{d1 + d2} = q^{d1} q^{d2}).
+// product with a power q^d of q plus a constant.  One wavefront walks one
+// instance, so all instances of a batch are resident at once and the latency
+// of one instance's chain of dependent steps is hidden by the others; the
+// polynomials live in a per-instance workspace in HBM (L2-resident while the
+// instance runs) and every product is a register-blocked convolution over the
+// wavefront.  The powers q^d are computed by the tree's power chain
+// (q^{d1 + d2} = q^{d1} q^{d2}).
 #include <hip/hip_runtime.h>
 
 #include "fpe_internal.h"
@@ -17,7 +20,7 @@ namespace fpe {
 
 namespace {
 
-constexpr int kCB = 256;   // threads per instance
+constexpr int kCB = 64;   // threads per instance: one wavefront
 
 __device__ __forceinline__ uint32_t m31_fold(uint64_t v) {
   v = (v & kP31) + (v >> 31);
@@ -39,25 +42,86 @@ struct ComposeArgs {
 
 // out[0 .. la + lb - 1) (+)= a * b, plus c0 at degree 0.  When accumulate is
 // set, out holds a polynomial of length lout that is extended with zeros.
-__device__ void poly_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uint32_t* out,
-                         int lout, bool accumulate, uint32_t c0) {
+//
+// Register-blocked convolution by one wavefront: lane l owns kR consecutive
+// output coefficients of a tile of 64 kR, and the loop runs over the shorter
+// operand a in chunks of kChunk coefficients.  For each chunk the slice of the
+// longer operand b that the tile needs (64 kR + kChunk - 1 words) and the
+// chunk of a are staged in LDS with coalesced loads; then, block by block of
+// kR coefficients of a, each lane reads a window of 2 kR - 1 words of b
+// (stride kR across lanes) and does kR * kR multiply-adds.  Products of
+// 31-bit residues are < 2^62, so a 64-bit accumulator takes three of them
+// between folds (2^31 = 1 mod p).
+constexpr int kR = 6;
+constexpr int kChunk = 11 * kR;   // a multiple of kR: windows stay inside the staged slice
+constexpr int kSpan = 64 * kR + kChunk;   // staged words of b per chunk
+
+__device__ __forceinline__ uint64_t m31_fold64(uint64_t v) { return (v & kP31) + (v >> 31); }
+
+__device__ void poly_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uint32_t* out, int lout,
+                         bool accumulate, uint32_t c0, uint32_t* sb, uint32_t* sa) {
+  if (la > lb) {   // loop over the shorter operand
+    const uint32_t* t = a;
+    a = b;
+    b = t;
+    const int tl = la;
+    la = lb;
+    lb = tl;
+  }
   const int lp = la + lb - 1;
-  for (int k = threadIdx.x; k < lp; k += kCB) {
-    const int i0 = k - lb + 1 > 0 ? k - lb + 1 : 0;
-    const int i1 = k < la - 1 ? k : la - 1;
-    uint64_t acc = 0;
-    int cnt = 0;
-    for (int i = i0; i <= i1; ++i) {
-      acc += (uint64_t)a[i] * b[k - i];
-      if (++cnt == 3) {   // three products < 2^62 stay below 2^64
-        acc = (acc & kP31) + (acc >> 31);
-        cnt = 0;
+  const int lane = threadIdx.x & 63;
+  for (int tile = 0; tile < lp; tile += 64 * kR) {
+    const int k0 = tile + lane * kR;
+    int i_lo = tile - (lb - 1);   // a's coefficients that reach this tile
+    if (i_lo < 0) i_lo = 0;
+    int i_hi = tile + 64 * kR - 1;
+    if (i_hi > la - 1) i_hi = la - 1;
+    uint64_t acc[kR];
+#pragma unroll
+    for (int r = 0; r < kR; ++r) acc[r] = 0;
+    for (int ic = i_lo; ic <= i_hi; ic += kChunk) {
+      // stage b[j0 .. j0 + kSpan) with j0 = tile - ic - (kChunk - 1), and
+      // a[ic .. ic + kChunk) (zero outside the operands)
+      const int j0 = tile - ic - (kChunk - 1);
+      __syncthreads();
+      for (int u = lane; u < kSpan; u += 64) {
+        const int j = j0 + u;
+        sb[u] = (j >= 0 && j < lb) ? b[j] : 0u;
+      }
+      for (int u = lane; u < kChunk; u += 64) {
+        const int i = ic + u;
+        sa[u] = (i <= i_hi) ? a[i] : 0u;
+      }
+      __syncthreads();
+      // window indices: base + m in [0, kSpan) because ib <= kChunk - kR
+      for (int ib = 0; ib < kChunk && ic + ib <= i_hi; ib += kR) {
+        // window bw[m] = b[k0 - (ic + ib) - (kR - 1) + m] = sb[base + m]
+        const int base = lane * kR + (kChunk - 1) - ib - (kR - 1);
+        uint32_t bw[2 * kR - 1];
+#pragma unroll
+        for (int m = 0; m < 2 * kR - 1; ++m) bw[m] = sb[base + m];
+#pragma unroll
+        for (int s2 = 0; s2 < kR; ++s2) {
+          const uint32_t av = sa[ib + s2];
+#pragma unroll
+          for (int r = 0; r < kR; ++r) acc[r] += (uint64_t)av * bw[r - s2 + kR - 1];
+          if (s2 % 3 == 2) {
+#pragma unroll
+            for (int r = 0; r < kR; ++r) acc[r] = m31_fold64(acc[r]);
+          }
+        }
       }
     }
-    acc = (acc & kP31) + (acc >> 31);
-    if (accumulate && k < lout) acc += out[k];
-    if (k == 0) acc += c0;
-    out[k] = m31_fold(acc);
+#pragma unroll
+    for (int r = 0; r < kR; ++r) {
+      const int k = k0 + r;
+      if (k < lp) {
+        uint64_t v = m31_fold64(acc[r]);
+        if (accumulate && k < lout) v += out[k];
+        if (k == 0) v += c0;
+        out[k] = m31_fold(v);
+      }
+    }
   }
 }
 
@@ -78,6 +142,7 @@ __global__ __launch_bounds__(kCB) void k_compose_walk(ComposeArgs A) {
   uint32_t* table = W + (int64_t)A.nbuf * A.lmax;          // n_table polynomials
   const uint32_t* coef = tr.coef_rows + inst * (int64_t)tr.n_nodes;
   const uint32_t* qi = A.q + inst * (int64_t)(A.dq + 1);
+  __shared__ uint32_t sb[kSpan], sa[kChunk];   // product staging (see poly_mac)
   __shared__ int32_t tab_len[kMaxTable];
   __shared__ int32_t buf[kMaxDepth + 2];   // stack level -> buffer
   __shared__ int32_t len[kMaxDepth + 2];   // length of the polynomial at each level
@@ -91,8 +156,7 @@ __global__ __launch_bounds__(kCB) void k_compose_walk(ComposeArgs A) {
       if (threadIdx.x == 0) tab_len[st.dst] = A.dq + 1;
     } else {
       const int la = tab_len[st.s1], lb = tab_len[st.s2];
-      poly_mac(table + (int64_t)st.s1 * A.lmax, la, table + (int64_t)st.s2 * A.lmax, lb, dst, 0,
-               false, 0);
+      poly_mac(table + (int64_t)st.s1 * A.lmax, la, table + (int64_t)st.s2 * A.lmax, lb, dst, 0, false, 0, sb, sa);
       if (threadIdx.x == 0) tab_len[st.dst] = la + lb - 1;
     }
     __syncthreads();
@@ -121,7 +185,7 @@ __global__ __launch_bounds__(kCB) void k_compose_walk(ComposeArgs A) {
     } else if (kind == kNodeOpen) {
       uint32_t* s = W + (int64_t)buf[top - 1] * A.lmax;
       uint32_t* d = W + (int64_t)buf[top] * A.lmax;   // free buffer above the top
-      poly_mac(s, len[top - 1], X, lx, d, 0, false, cP);
+      poly_mac(s, len[top - 1], X, lx, d, 0, false, cP, sb, sa);
       __syncthreads();
       if (threadIdx.x == 0) {
         const int b = buf[top - 1];
@@ -138,7 +202,7 @@ __global__ __launch_bounds__(kCB) void k_compose_walk(ComposeArgs A) {
     } else if (kind == kNodeAdd) {
       uint32_t* s = W + (int64_t)buf[top - 1] * A.lmax;
       uint32_t* d = W + (int64_t)buf[top - 2] * A.lmax;
-      poly_mac(s, len[top - 1], X, lx, d, len[top - 2], true, 0);
+      poly_mac(s, len[top - 1], X, lx, d, len[top - 2], true, 0, sb, sa);
       __syncthreads();
       if (threadIdx.x == 0) len[top - 2] = max(len[top - 2], len[top - 1] + lx - 1);
       --top;
@@ -154,7 +218,7 @@ __global__ __launch_bounds__(kCB) void k_compose_walk(ComposeArgs A) {
       } else {
         const uint32_t* s = W + (int64_t)buf[top - 1] * A.lmax;
         if (pw) {
-          poly_mac(s, len[top - 1], X, lx, res, 0, false, 0);
+          poly_mac(s, len[top - 1], X, lx, res, 0, false, 0, sb, sa);
           lr = len[top - 1] + lx - 1;
         } else {
           for (int k = threadIdx.x; k < len[top - 1]; k += kCB) res[k] = s[k];
