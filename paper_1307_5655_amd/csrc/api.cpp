@@ -43,6 +43,7 @@ DevTree dev_view(const fpe_tree* t) {
   d.nvars = t->nvars;
   d.depth = t->depth;
   d.n_nodes = (int32_t)t->nodes.size();
+  d.n_offtable = t->n_offtable;
   d.batch = t->batch;
   return d;
 }

@@ -108,6 +108,7 @@ struct DevTree {
   int32_t nvars;
   int32_t depth;               // max stack depth of the walk
   int32_t n_nodes;
+  int32_t n_offtable;          // walk steps whose power is computed on the fly
   int64_t batch;
 };
 

@@ -1,7 +1,7 @@
 // Fused served launches: one work table of requests (different trees, point
 // counts and forms) in one launch over a fixed grid that strides over the
 // 64-point blocks of all requests.  Served trees may hold powers outside the
-// table (computed on the fly), so these kernels take that path too.
+// table (computed on the fly), so these kernels carry that path too.
 #include "walk_core.h"
 
 namespace fpe {
@@ -42,7 +42,10 @@ __global__ __launch_bounds__(kBlock) void k_serve_walk(WorkTable* wt) {
       const double y = walk_point<ArF64, DMAX, true>(it.tree, x, lds);
       if (in) it.out[i] = y;
     } else {
-      const DF rr = walk_point<ArDF32, DMAX, true>(it.tree, x, lds);
+      // the walk without on-the-fly powers (no coordinates kept) when the
+      // tree has none, which is the usual case
+      const DF rr = it.tree.n_offtable == 0 ? walk_point<ArDF32, DMAX, false>(it.tree, x, lds)
+                                            : walk_point<ArDF32, DMAX, true>(it.tree, x, lds);
       if (in) {
         double y;
         float cond;
@@ -55,25 +58,38 @@ __global__ __launch_bounds__(kBlock) void k_serve_walk(WorkTable* wt) {
   }
 }
 
+// The flagged points of all requests of the batch, cut into 64-point blocks
+// per request, form one index space: each workgroup builds the prefix of the
+// per-request block counts in LDS, then the grid strides over the blocks
+// (binary search for the request), so the work is spread evenly whatever the
+// mix of request sizes, and every wavefront walks one request's tree.
 template <int DMAX>
 __global__ __launch_bounds__(kBlock) void k_serve_fallback(WorkTable* wt) {
   const int n = wt->n_items;
   const WorkItem* items = table_items(wt);
   const int64_t* counters = table_counters(wt);
   extern __shared__ __align__(16) char lds[];
-  for (int r = 0; r < n; ++r) {
-    const WorkItem& it = items[r];
-    if (it.domain != FPE_F32C) continue;
-    const int64_t cnt = counters[r];
-    for (int64_t base = (int64_t)blockIdx.x * kBlock; base < cnt; base += (int64_t)gridDim.x * kBlock) {
-      const int64_t k = base + threadIdx.x;
-      const int64_t i = k < cnt ? it.list[k] : -1;
-      double x[8];
-#pragma unroll
-      for (int j = 0; j < 8; ++j) x[j] = (i >= 0 && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
-      const DD rr = walk_point<ArDD, DMAX, true>(it.tree, x, lds);
-      if (i >= 0) it.out[i] = rr.h + rr.l;
+  __shared__ int64_t pre[kMaxServe + 1];
+  if (threadIdx.x == 0) {
+    int64_t acc = 0;
+    for (int r = 0; r < n; ++r) {
+      pre[r] = acc;
+      acc += items[r].domain == FPE_F32C ? (counters[r] + kBlock - 1) / kBlock : 0;
     }
+    pre[n] = acc;
+  }
+  __syncthreads();
+  const int64_t total = pre[n];
+  for (int64_t b = blockIdx.x; b < total; b += gridDim.x) {
+    const int r = find_item(pre, n, b);
+    const WorkItem& it = items[r];
+    const int64_t k = (b - pre[r]) * kBlock + threadIdx.x;
+    const int64_t i = k < counters[r] ? it.list[k] : -1;
+    double x[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) x[j] = (i >= 0 && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
+    const DD rr = walk_point<ArDD, DMAX, true>(it.tree, x, lds);
+    if (i >= 0) it.out[i] = rr.h + rr.l;
   }
 }
 

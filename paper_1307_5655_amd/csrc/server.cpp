@@ -183,7 +183,7 @@ fpe_status build_slot(fpe_server* s, Slot& sl) {
     hipKernelNodeParams fp = wp;
     fp.func = (void*)(c == 0 ? K.fallback8 : K.fallback16);
     fp.sharedMemBytes = (unsigned)K.fallback_lds;
-    fp.gridDim = dim3(kServeGrid / 4);
+    fp.gridDim = dim3(kServeGrid);
     if (hipGraphAddKernelNode(&f, sl.graph, &w, 1, &fp) != hipSuccess)
       return fail(FPE_EDEVICE, "server: graph kernel node failed");
     if (hipGraphAddMemcpyNode1D(&back, sl.graph, &f, 1, sl.host_counters[c], table_counters(sl.dev[c]),
