@@ -1,6 +1,6 @@
 // Host-side launch of the pointwise walks (fpe_evaluate): picks the kernel
 // by domain, walk depth, points per lane and whether any power is computed
-// on the fly, and sizes each wavefront's LDS power table.
+// on the fly; the kernels' launchers size the LDS tier of the power tables.
 #include "walk_core.h"
 
 namespace fpe {

@@ -1,12 +1,13 @@
 // Evaluation-tree walk core for gfx950 (CDNA4), shared by the kernels.
 //
-// One point per lane; the node program (the walk of Section 2.1 in stack
+// PPL points per lane; the node program (the walk of Section 2.1 in stack
 // form, see fpe_internal.h) is wave-uniform and read with scalar loads, so
 // the whole wavefront shares each op.  The accumulators of the walk live in
-// VGPRs: the kernel is a nest of loops, one per stack depth, so every
-// accumulator index is a compile-time constant.  The per-point powers x_j^d
-// (Section 2.2, fast exponentiation) are computed once per point by the
-// tree's power chain into a register table before the walk.
+// VGPRs: one switch on each op's dispatch code, whose cases carry the stack
+// depth as a compile-time constant, so every accumulator index is static.
+// The per-point powers x_j^d (Section 2.2, fast exponentiation) are computed
+// once per point by the tree's power chain into a per-point table before the
+// walk (registers, an LDS tier and private memory; see "power tables").
 //
 // Arithmetic policies:
 //   F64   plain FP64, one fused multiply-add per node;
@@ -304,13 +305,10 @@ struct ArDF32 {
 // power tables
 // ----------------------------------------------------------------------------
 //
-// Each point owns one column of a per-wavefront table in LDS: entry e of
-// column c (= point-in-lane j * 64 + lane) at [e][c], so a wavefront reads 64
-// consecutive words (no bank conflict).  The two most used entries are also
-// kept in registers.  The chain runs in double-double with the low word
-// stored as a float relative to the high word (lo / hi, so it cannot overflow
-// where hi is large): about 77 bits, so every power is accurate to a few units
-// in 2^-70 before it is rounded.
+// The chain runs in double-double (the FP64 table keeps the low word as a
+// float relative to the high word, lo / hi, so it cannot overflow where hi is
+// large: about 77 bits), so every power is accurate to a few units in 2^-70
+// before it is rounded.
 
 constexpr int kWave = 64;
 
@@ -326,7 +324,8 @@ __device__ __forceinline__ float rel_lo(const DD& r) {
 // for the walk.  The table takes no LDS and no registers beyond those
 // copies, so occupancy is set by the walk's accumulators.
 
-// Register copies of entries 0..3 (static indices) and the dynamic reader.
+// Register copies of entries 0..kRegPowers-1 (static indices) and the
+// dynamic reader.
 template <class E>
 struct RegPow {
   E r[kRegPowers];
@@ -535,8 +534,9 @@ struct Walker {
   }
 
 #define FPE_FOR_J _Pragma("unroll") for (int j = 0; j < PPL; ++j)
-  // X for point j in power class PC (see PowClass): registers, one LDS
-  // entry, or (class 3) the product of two entries / computed on the fly.
+  // X for point j in power class PC (see PowClass): a register entry, one
+  // entry of the LDS tier or private table (kPowMem), or (kPowOther) the
+  // product of two or three entries / a power computed on the fly.
   template <uint32_t PC>
   __device__ __forceinline__ Pow power(const Op& o, int j) const {
     if constexpr (PC < (uint32_t)kRegPowers) {
