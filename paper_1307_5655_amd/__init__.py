@@ -245,7 +245,8 @@ def workspace_bytes(tree: Tree, npts: int) -> int:
 
 
 def evaluate(tree: Tree, pts, out=None, tol: float = 1e-12, force: int = 0, cond_out=None,
-             flags_out=None, workspace=None, nfallback_out=None, stream=None, events=None):
+             flags_out=None, workspace=None, nfallback_out=None, stream=None, events=None,
+             points_per_lane: int = 0):
     """Evaluate ``tree`` at device points ``pts`` (list of 1-D tensors, one per
     variable; float64, or uint64 residues stored as int64 for FPE_MODP)."""
     import torch
@@ -257,7 +258,7 @@ def evaluate(tree: Tree, pts, out=None, tol: float = 1e-12, force: int = 0, cond
         dt = torch.int64 if tree.domain == MODP else torch.float64
         out = torch.empty(npts, dtype=dt, device=pts[0].device)
     arr = (ctypes.c_void_p * 8)(*[p.data_ptr() for p in pts])
-    opts = EvalOpts(tol, force, 0, cond_out.data_ptr() if cond_out is not None else None,
+    opts = EvalOpts(tol, force, points_per_lane, cond_out.data_ptr() if cond_out is not None else None,
                     flags_out.data_ptr() if flags_out is not None else None, None, 0,
                     nfallback_out.data_ptr() if nfallback_out is not None else None)
     if events is not None:

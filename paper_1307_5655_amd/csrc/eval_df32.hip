@@ -73,10 +73,10 @@ static void go(const KernelLaunch& L, const F32COut& o) {
   Pts<double> P{};
   for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const double*)L.pts[j];
   if (o.cond)
-    hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT, true>), dim3((unsigned)L.nblocks), dim3(kBlock),
+    hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT, true>), dim3((unsigned)blocks_for(L.npts, PPL)), dim3(kBlock),
                        (walk_lds_bytes<ArDF32, DMAX, PPL>()), L.stream, L.tr, P, L.npts, o);
   else
-    hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT, false>), dim3((unsigned)L.nblocks), dim3(kBlock),
+    hipLaunchKernelGGL((k_eval_df32<DMAX, PPL, OFFT, false>), dim3((unsigned)blocks_for(L.npts, PPL)), dim3(kBlock),
                        (walk_lds_bytes<ArDF32, DMAX, PPL>()), L.stream, L.tr, P, L.npts, o);
 }
 

@@ -23,7 +23,7 @@ template <int DMAX, int PPL, bool OFFT>
 static void go(const KernelLaunch& L, double* out) {
   Pts<double> P{};
   for (int j = 0; j < L.tr.nvars; ++j) P.p[j] = (const double*)L.pts[j];
-  hipLaunchKernelGGL((k_eval_f64<DMAX, PPL, OFFT>), dim3((unsigned)L.nblocks), dim3(kBlock),
+  hipLaunchKernelGGL((k_eval_f64<DMAX, PPL, OFFT>), dim3((unsigned)blocks_for(L.npts, PPL)), dim3(kBlock),
                      (walk_lds_bytes<ArF64, DMAX, PPL>()), L.stream, L.tr, P, L.npts, out);
 }
 

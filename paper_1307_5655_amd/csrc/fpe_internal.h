@@ -203,13 +203,16 @@ __host__ __device__ inline int64_t* table_counters(WorkTable* t) { return table_
 
 // One pointwise launch (walk.hip picks the shape; the eval_*.hip files hold
 // the kernels).
+// Workgroups (one wavefront each) for n points at ppl points per lane.
+inline int64_t blocks_for(int64_t n, int ppl) { return (n + 64 * ppl - 1) / (64 * ppl); }
+
 struct KernelLaunch {
   DevTree tr;
   const void* pts[8];
   int64_t npts;
-  int64_t nblocks;
+  int64_t nblocks;   // fixed grid of the fallback kernels (the walks size theirs from their PPL)
   hipStream_t stream;
-  int ppl;
+  int ppl;           // requested points per lane (the launchers pick a kernel at most this wide)
   bool offt;
 };
 struct F32COut;

@@ -15,7 +15,6 @@ size_t eval_workspace_bytes(const fpe_tree* t, int64_t npts) {
 
 namespace {
 
-inline int64_t blocks_for(int64_t n, int ppl) { return (n + kBlock * ppl - 1) / (kBlock * ppl); }
 
 // Points per lane: one op drives PPL independent multiply-adds, which
 // amortises the wave-uniform dispatch; tables beyond kTableCapMulti entries
@@ -46,7 +45,6 @@ fpe_status launch_eval(const fpe_tree* t, const void* const* pts, int64_t npts, 
   L.npts = npts;
   L.ppl = pick_ppl(t, opts);
   L.offt = t->n_offtable > 0;
-  L.nblocks = blocks_for(npts, L.ppl);
   L.stream = st;
   hipEvent_t eb = opts ? (hipEvent_t)opts->ev_walk_begin : nullptr;
   hipEvent_t ee = opts ? (hipEvent_t)opts->ev_walk_end : nullptr;

@@ -79,6 +79,32 @@ def test_deep_estrin_walks(dev, log2n, depth):
     assert np.array_equal(got, want)
 
 
+@pytest.mark.parametrize("scheme", ["horner", "estrin", "balanced"])
+def test_points_per_lane_requests_give_the_same_bits(dev, scheme):
+    """Whatever width is requested, the launcher runs a kernel at most that
+    wide with a grid sized for it: every point is written, with the same bits."""
+    say(f"points per lane 1..16 {scheme}")
+    inp = fpe_inputs.sparse_uni(3000, npts=10_000 + 77, lo=-0.99, hi=0.99)
+    e = np.nonzero(inp.coeffs)[0].astype(np.int32).reshape(-1, 1)
+    x = to_dev(inp.points, dev)
+    for dom in (fpe.F64, fpe.F32C):
+        t = fpe.Tree(e, inp.coeffs[e[:, 0]], scheme, dom).upload(dev)
+        ref = fpe.evaluate(t, [x]).cpu().numpy()
+        for ppl in (1, 2, 3, 4, 8, 16):
+            out = torch.full((len(inp.points),), float("nan"), dtype=torch.float64, device=dev)
+            fpe.evaluate(t, [x], out=out, points_per_lane=ppl)
+            y = out.cpu().numpy()
+            assert np.array_equal(y.view(np.uint64), ref.view(np.uint64)), (dom, ppl)
+    m = fpe_inputs.random_modp_poly(2, 400, 30, 5000 + 9, seed=(77,))
+    t = fpe.Tree(m.exps, m.coeffs, scheme, fpe.MODP, fpe.P61).upload(dev)
+    px = [to_dev(m.points[j].view(np.int64), dev) for j in range(2)]
+    ref = fpe.evaluate(t, px).cpu().numpy()
+    for ppl in (1, 2, 4, 8):
+        out = torch.full((m.points.shape[1],), -1, dtype=torch.int64, device=dev)
+        fpe.evaluate(t, px, out=out, points_per_lane=ppl)
+        assert np.array_equal(out.cpu().numpy(), ref), ppl
+
+
 def test_dense_horner_bit_identical_to_fma_horner(dev):
     say("dense n=1023 horner bit-exact")
     inp = fpe_inputs.dense_uni(npts=5000)
