@@ -105,6 +105,30 @@ def test_points_per_lane_requests_give_the_same_bits(dev, scheme):
         assert np.array_equal(out.cpu().numpy(), ref), ppl
 
 
+@pytest.mark.parametrize("which", ["threshold", "table"])
+def test_threshold_and_table_schemes(dev, which):
+    """User schemes (Section 1.2: Estrin above a threshold degree and Hörner
+    below; an arbitrary legal table f(n) in [1, n]) on every domain."""
+    say(f"scheme {which}")
+    inp = fpe_inputs.sparse_uni(1500, npts=6000 + 13, lo=-1.0, hi=1.0)
+    e = np.nonzero(inp.coeffs)[0].astype(np.int32).reshape(-1, 1)
+    c = inp.coeffs[e[:, 0]]
+    if which == "threshold":
+        kw = dict(threshold=24)
+    else:
+        g = np.random.default_rng([13075655, 700])
+        kw = dict(table=[0] + [int(g.integers(1, n + 1)) for n in range(1, 1502)])
+    x = to_dev(inp.points, dev)
+    t = fpe.Tree(e, c, which, fpe.F64, **kw).upload(dev)
+    check_f64(fpe.evaluate(t, [x]).cpu().numpy(), inp.coeffs, inp.points)
+    t = fpe.Tree(e, c, which, fpe.F32C, **kw).upload(dev)
+    check_f32c(fpe.evaluate(t, [x]).cpu().numpy(), inp.coeffs, inp.points)
+    m = fpe_inputs.random_modp_poly(1, 1501, 1500, 2000 + 3, seed=(701,))
+    t = fpe.Tree(m.exps, m.coeffs, which, fpe.MODP, fpe.P61, **kw).upload(dev)
+    got = fpe.evaluate(t, [to_dev(m.points[0].view(np.int64), dev)]).cpu().numpy().view(np.uint64)
+    assert np.array_equal(got, native.modp_eval(m.exps, m.coeffs, fpe.P61, m.points))
+
+
 def test_dense_horner_bit_identical_to_fma_horner(dev):
     say("dense n=1023 horner bit-exact")
     inp = fpe_inputs.dense_uni(npts=5000)
