@@ -39,11 +39,16 @@ FP32_VALU_PEAK = 256 * 128 * 2.4e9
 FP64_FMA_PEAK = 256 * 64 * 2.4e9
 # FP32 operations of one compensated multiply-add a * X + b: product and its
 # error by fma (2), three cross terms (3), TwoSum (6), two low-order adds (2),
-# FastTwoSum (3) and the running error bound (3 fma).  The condition sum
-# (1 more fma) is computed only when per-point condition numbers are
-# requested, which the timed step does not do (the condition numbers of the
-# workload are reported from the oracle's sample instead).
-DF32_OPS_PER_TERM = 19
+# FastTwoSum (3), then the running error bound: e_a |X| + e_b (1 fma, when
+# the product's operand is an accumulator), 20 u^2 |p| (1 fma) and 6 u^2 |b|
+# (1 fma when b is an accumulator; a coefficient's term is a constant of the
+# op).  Per step kind: LEAF_ADD a X + top 18, NODE_OPEN top X + b 18,
+# LEAF_OPEN a X + b 17, NODE_ADD top X + below 19; END (once per point) is not
+# counted.  The condition sum (1 more fma) is computed only when per-point
+# condition numbers are requested, which the timed step does not do (the
+# condition numbers of the workload are reported from the oracle's sample
+# instead).
+DF32_OPS_BY_KIND = (18, 18, 17, 19, 0)
 
 
 def log(msg):
@@ -248,7 +253,7 @@ def main():
     schemes = ("balanced", "estrin", "horner")
     forms = (("f32c", fpe.F32C), ("f64", fpe.F64))
     inputs, trees, xs, outs, ws, nfb = {}, {}, {}, {}, {}, {}
-    term_evals = {}
+    term_evals, df_step_ops = {}, {}
     for n in degrees:
         inp = fpe_inputs.sparse_uni(n, npts=args.points)
         inputs[n] = inp
@@ -260,6 +265,8 @@ def main():
                 trees[(n, s, fname)] = t
                 outs[(n, s, fname)] = torch.empty(args.points, dtype=torch.float64, device=dev)
                 term_evals[(n, s, fname)] = float(t.info.n_terms) * args.points
+                df_step_ops[(n, s, fname)] = float(sum(
+                    k * o for k, o in zip(t.info.n_ops_kind, DF32_OPS_BY_KIND))) * args.points
                 if dom == fpe.F32C:
                     ws[(n, s)] = torch.empty(fpe.workspace_bytes(t, args.points) + 256, dtype=torch.uint8,
                                              device=dev)
@@ -308,7 +315,7 @@ def main():
 
     # dominant kernel: the compensated-FP32 walk (most of the step's time)
     df_keys = [k for k in keys if k[2] == "f32c"]
-    df_ops = sum(term_evals[k] * DF32_OPS_PER_TERM for k in df_keys)
+    df_ops = sum(df_step_ops[k] for k in df_keys)
     df_time = sum(walk_ms[k] for k in df_keys) * 1e-3
     f64_keys = [k for k in keys if k[2] == "f64"]
     f64_fma = sum(term_evals[k] for k in f64_keys)
@@ -322,7 +329,7 @@ def main():
         "unit": "TOP/s (FP32 VALU lane-ops)",
         "frac": (df_ops / df_time) / FP32_VALU_PEAK,
         "traffic": traffic,
-        "ops_per_term_eval": DF32_OPS_PER_TERM,
+        "ops_per_term_eval": df_ops / sum(term_evals[k] for k in df_keys),
         "avg_launch_ms": df_time * 1e3 / len(df_keys),
     }
     roofline_f64 = {

@@ -138,6 +138,8 @@ typedef struct {
   int32_t n_chain;         /* steps of the power chain (Section 2.2, fast exponentiation) */
   int32_t n_offtable;      /* walk steps whose power is computed on the fly */
   int32_t n_pair_ops;      /* walk steps whose power is the product of two table entries */
+  int32_t n_ops_kind[5];   /* walk steps by kind: LEAF_ADD (a X + top), NODE_OPEN (top X + b),
+                              LEAF_OPEN (push a X + b), NODE_ADD (below += top X; pop), END */
 } fpe_tree_info;
 
 fpe_status fpe_tree_get_info(const fpe_tree* t, fpe_tree_info* info);

@@ -48,7 +48,8 @@ class TreeInfo(ctypes.Structure):
                 ("max_slot", ctypes.c_int32), ("max_lazy_height", ctypes.c_int32),
                 ("walk_depth", ctypes.c_int32), ("n_powers", ctypes.c_int32),
                 ("n_table", ctypes.c_int32), ("n_chain", ctypes.c_int32),
-                ("n_offtable", ctypes.c_int32), ("n_pair_ops", ctypes.c_int32)]
+                ("n_offtable", ctypes.c_int32), ("n_pair_ops", ctypes.c_int32),
+                ("n_ops_kind", ctypes.c_int32 * 5)]
 
 
 class EvalOpts(ctypes.Structure):
@@ -77,6 +78,11 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() or "
                           "python paper_1307_5655_amd/build.py")
+    # Device buffers and stream handles come from PyTorch, so the library must
+    # bind to the HIP runtime PyTorch loaded: import it first, so that the
+    # dynamic loader resolves libfpe's libamdhip64 to that copy instead of
+    # loading a second runtime (which then finds no device of its own).
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     P, i32, i64, u64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
     sig = {

@@ -44,6 +44,7 @@ DevTree dev_view(const fpe_tree* t) {
   d.depth = t->depth;
   d.n_nodes = (int32_t)t->nodes.size();
   d.n_offtable = t->n_offtable;
+  d.bound_scale = df32_bound_scale(d.n_ops);
   d.batch = t->batch;
   return d;
 }
@@ -96,6 +97,7 @@ fpe_status fpe_tree_get_info(const fpe_tree* t, fpe_tree_info* info) {
   info->n_chain = (int32_t)t->chain.size();
   info->n_offtable = t->n_offtable;
   info->n_pair_ops = t->n_pairs;
+  for (int k = 0; k < 5; ++k) info->n_ops_kind[k] = t->n_kind[k];
   return FPE_OK;
 }
 

@@ -68,9 +68,15 @@ inline void split_f32(double v, float& h, float& l) {
   l = (float)(v - (double)h);
 }
 
-inline float abs_up(double v) {
-  float f = (float)std::fabs(v);
-  return f == 0.f ? 0.f : std::nextafter(f, INFINITY);
+// K2 |bh| rounded up, bh = b rounded to float: the running-bound term of an
+// exact constant b in one double-float step (see the double-float walk: the
+// step's new error is at most u^2 (17 |p| + 4 |b|) with u = 2^-24, taken with
+// constants 20 and 6).
+inline float bound_term_up(double b) {
+  const double v = 6.0 * std::ldexp(1.0, -48) * std::fabs((double)(float)b);   // exact in FP64
+  float f = (float)v;
+  if ((double)f < v) f = std::nextafter(f, INFINITY);
+  return f;
 }
 
 }  // namespace
@@ -685,6 +691,7 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
       maxd = std::max(maxd, depth);
     }
     op.info = info;
+    t->n_kind[op_kind(info)]++;
     {
       // dispatch code: depth, kind, power class (END: depth 0, kind 0)
       uint32_t pc = kPowOther;
@@ -709,8 +716,7 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
       std::memcpy(&b, &o.b, 8);
       split_f32(a, q.ah, q.al);
       split_f32(b, q.bh, q.bl);
-      q.aabs = abs_up(a);
-      q.babs = abs_up(b);
+      q.bk2 = bound_term_up(b);
       q.info = o.info;
       q.deg = o.deg;
       t->ops32[i] = q;

@@ -23,7 +23,7 @@ __global__ __launch_bounds__(kBlock) void k_eval_df32(DevTree tr, Pts<double> P,
     if (i < npts) {
       double y;
       float cond;
-      flag = df32_finish<COND>(r[j], o.tol, o.force, y, cond);
+      flag = df32_finish<COND>(r[j], o.tol, tr.bound_scale, o.force, y, cond);
       o.out[i] = y;
       if constexpr (COND) o.cond[i] = cond;
     }

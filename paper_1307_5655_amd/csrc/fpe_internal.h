@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <stddef.h>
 
+#include <cmath>
 #include <string>
 #include <vector>
 
@@ -82,8 +83,8 @@ struct alignas(32) OpF32 {   // double-float walk: constants pre-split on the ho
   float bh, bl;
   uint32_t info;
   uint32_t deg;
-  float aabs;                // |a| rounded up, for the condition sum
-  float babs;
+  float bk2;                 // kK2 * |bh| rounded up: the bound term of an exact b
+  float pad;
 };
 static_assert(sizeof(OpF32) == 32, "OpF32 is one 32-byte scalar load");
 
@@ -109,6 +110,7 @@ struct DevTree {
   int32_t depth;               // max stack depth of the walk
   int32_t n_nodes;
   int32_t n_offtable;          // walk steps whose power is computed on the fly
+  float bound_scale;           // double-float walk: factor on the final error bound
   int64_t batch;
 };
 
@@ -161,12 +163,22 @@ struct fpe_tree {
   int32_t max_lh = 0;
   int32_t n_offtable = 0;
   int32_t n_pairs = 0;
+  int32_t n_kind[5] = {};   // walk ops by OpKind
   // device image
   void* dev = nullptr;
   size_t off_ops64 = 0, off_ops32 = 0, off_chain = 0, off_coef = 0, dev_bytes = 0;
 };
 
 namespace fpe {
+// Factor on the double-float walk's final error bound that covers the FP32
+// evaluation of the bound over n steps (at most (1 + 4.001 u)^n, u = 2^-24),
+// with 2^-20 to spare for the final test's own roundings; rounded up.
+inline float df32_bound_scale(int64_t n_steps) {
+  const double g = std::exp((double)n_steps * 4.001 * std::ldexp(1.0, -24)) * (1.0 + std::ldexp(1.0, -20));
+  float f = (float)g;
+  if ((double)f < g) f = std::nextafter(f, INFINITY);
+  return f;
+}
 void set_error(const std::string& msg);
 fpe_status fail(fpe_status st, const std::string& msg);
 DevTree dev_view(const fpe_tree* t);

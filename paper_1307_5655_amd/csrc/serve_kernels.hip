@@ -49,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_serve_walk(WorkTable* wt) {
       if (in) {
         double y;
         float cond;
-        flag = df32_finish<true>(rr, it.tol, 0, y, cond);
+        flag = df32_finish<true>(rr, it.tol, it.tree.bound_scale, 0, y, cond);
         it.out[i] = y;
         if (it.cond) it.cond[i] = cond;
       }

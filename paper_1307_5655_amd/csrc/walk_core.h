@@ -209,8 +209,15 @@ struct ArM61 {
 // round by at most u^2 (7|p| + 3|b|); the 48-bit constants a and b add
 // u^2 (|p| + |b|).  The new error is therefore at most u^2 (17|p| + 4|b|);
 // the bound uses 20 and 6 for margin, and inherited errors propagate as
-// e_a |X| + e_b.  The FP32 evaluation of the bound itself loses at most a
-// factor (1 - u)^n, covered by the final factor 1.01.
+// e_a |X| + e_b.  When b is a coefficient (exact), the host stores 6 u^2 |b.h|
+// rounded up in the op, so that term costs nothing on the device.
+// The bound is evaluated in FP32 with |X.h| in place of |X|
+// (|X| <= |X.h| (1 + u + u^2)) and at most three roundings per step, each
+// shrinking a sum of non-negative terms by at most (1 - u): after n steps the
+// computed bound falls short of the exact one by at most
+// g^n, g = (1 + u + u^2) / (1 - u)^3 < 1 + 4.001 u.  The host gives every
+// tree the factor g^(n_ops) (with a little margin) as DevTree::bound_scale, and
+// the final test scales the bound by it.
 struct DF {
   float h, l, e, t;
 };
@@ -223,7 +230,7 @@ constexpr float kK1 = 20.0f * kU2;
 constexpr float kK2 = 6.0f * kU2;
 
 // EA / EB: whether a / b carry an inherited error bound (accumulators do;
-// the coefficients of a node are exact, so their terms are left out).
+// the coefficients of a node are exact and have no inherited term).
 template <bool EA, bool EB>
 __device__ __forceinline__ DF df_step(float ah, float al, float ea, float ta, const P3& X,
                                       float bh, float bl, float eb, float tb) {
@@ -238,14 +245,11 @@ __device__ __forceinline__ DF df_step(float ah, float al, float ea, float ta, co
   se = se + (pe + bl);
   float hi = s + se;
   float lo = se - (hi - s);
-  float ax = __builtin_fabsf(X.h) * 1.0000001f;
-  float e;
-  if constexpr (EA && EB) e = __builtin_fmaf(ea, ax, eb);
-  else if constexpr (EA) e = ea * ax;
-  else if constexpr (EB) e = eb;
-  else e = 0.f;
+  const float ax = __builtin_fabsf(X.h);
+  // eb: the inherited bound of b (EB), else b's own bound term 6 u^2 |b.h|
+  float e = EA ? __builtin_fmaf(ea, ax, eb) : eb;
   e = __builtin_fmaf(kK1, __builtin_fabsf(p), e);
-  e = __builtin_fmaf(kK2, __builtin_fabsf(bh), e);
+  if constexpr (EB) e = __builtin_fmaf(kK2, __builtin_fabsf(bh), e);
   float t = __builtin_fmaf(ta, ax, tb);
   return DF{hi, lo, e, t};
 }
@@ -257,18 +261,19 @@ struct ArDF32 {
   using In = double;
   static __device__ __forceinline__ const Op* ops(const DevTree& t) { return t.ops32; }
   static __device__ __forceinline__ Acc fma_ca(const Op& o, const Pow& X, const Acc& top) {
-    return df_step<false, true>(o.ah, o.al, 0.f, o.aabs, X, top.h, top.l, top.e, top.t);
+    return df_step<false, true>(o.ah, o.al, 0.f, __builtin_fabsf(o.ah), X, top.h, top.l, top.e, top.t);
   }
   static __device__ __forceinline__ Acc fma_tb(const Acc& top, const Pow& X, const Op& o) {
-    return df_step<true, false>(top.h, top.l, top.e, top.t, X, o.bh, o.bl, 0.f, o.babs);
+    return df_step<true, false>(top.h, top.l, top.e, top.t, X, o.bh, o.bl, o.bk2, __builtin_fabsf(o.bh));
   }
   static __device__ __forceinline__ Acc fma_ab(const Op& o, const Pow& X) {
-    return df_step<false, false>(o.ah, o.al, 0.f, o.aabs, X, o.bh, o.bl, 0.f, o.babs);
+    return df_step<false, false>(o.ah, o.al, 0.f, __builtin_fabsf(o.ah), X, o.bh, o.bl, o.bk2,
+                                  __builtin_fabsf(o.bh));
   }
   static __device__ __forceinline__ Acc fma_tt(const Acc& top, const Pow& X, const Acc& below) {
     return df_step<true, true>(top.h, top.l, top.e, top.t, X, below.h, below.l, below.e, below.t);
   }
-  static __device__ __forceinline__ Acc leaf_root(const Op& o) { return DF{o.ah, o.al, 0.f, o.aabs}; }
+  static __device__ __forceinline__ Acc leaf_root(const Op& o) { return DF{o.ah, o.al, 0.f, __builtin_fabsf(o.ah)}; }
   static __device__ __forceinline__ Acc mul(const Acc& a, const Pow& X) {
     return df_step<true, false>(a.h, a.l, a.e, a.t, X, 0.f, 0.f, 0.f, 0.f);
   }
@@ -760,10 +765,11 @@ struct F32COut {
 // decision does not use the condition sum, so it is the same whether or not
 // COND (the condition number p~(|x|) / |y| as output) is computed.
 template <bool COND>
-__device__ __forceinline__ bool df32_finish(const DF& r, double tol, int force, double& y, float& cond) {
+__device__ __forceinline__ bool df32_finish(const DF& r, double tol, float scale, int force, double& y,
+                                            float& cond) {
   y = (double)r.h + (double)r.l;
   const double ay = fabs(y);
-  const double bound = (double)r.e * 1.01;
+  const double bound = (double)r.e * (double)scale;
   const bool finite = isfinite(r.h) && isfinite(r.l) && isfinite(r.e);
   if constexpr (COND) cond = (float)((double)r.t / ay);
   bool flag = !finite || !(bound <= tol * ay) || ay < 1e-30;

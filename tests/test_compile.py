@@ -191,3 +191,19 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(fpe.lib, n), n
     assert set(fpe.EXPORTED) <= names
     assert fpe.lib.fpe_version().decode().startswith("fpe")
+
+
+def test_package_binds_to_one_hip_runtime():
+    # Importing the package before torch must not load a second HIP runtime
+    # next to the one PyTorch brings (that second copy finds no device once
+    # PyTorch's has opened it).  Checked in a fresh process.
+    import subprocess
+    import sys
+    code = ("import paper_1307_5655_amd\n"
+            "import torch\n"
+            "maps = open('/proc/self/maps').read().split('\\n')\n"
+            "libs = {l.split()[-1] for l in maps if 'libamdhip64' in l}\n"
+            "print(len(libs))\n")
+    r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stderr
+    assert r.stdout.strip().splitlines()[-1] == "1"
