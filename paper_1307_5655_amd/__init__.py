@@ -191,7 +191,7 @@ class Tree:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
+        if h and lib is not None:   # lib is None while the interpreter shuts down
             lib.fpe_tree_free(h)
             self._h = None
 
@@ -343,7 +343,7 @@ class Server:
         return s
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and lib is not None:
             lib.fpe_server_destroy(self._h)
             self._h = None
 

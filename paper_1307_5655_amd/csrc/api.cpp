@@ -17,11 +17,11 @@ inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 void layout(fpe_tree* t) {
   size_t off = 0;
-  // each op array is followed by one zero record (the walk reads one op ahead)
+  // each op array is followed by kOpTail zero records (the walk reads ahead)
   t->off_ops64 = off;
-  off = align256(off + (t->ops64.size() + 1) * sizeof(OpF64));
+  off = align256(off + (t->ops64.size() + kOpTail) * sizeof(OpF64));
   t->off_ops32 = off;
-  off = align256(off + (t->ops32.size() + 1) * sizeof(OpF32));
+  off = align256(off + (t->ops32.size() + kOpTail) * sizeof(OpF32));
   t->off_chain = off;
   off = align256(off + std::max<size_t>(t->chain.size(), 1) * sizeof(ChainStep));
   t->off_coef = off;
@@ -116,14 +116,14 @@ fpe_status fpe_tree_upload(fpe_tree* t, void* dev_buf, size_t bytes, void* strea
   if (((uintptr_t)dev_buf) & 255) return fail(FPE_EINVAL, "device buffer must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   char* b = (char*)dev_buf;
-  // the zero record after each op array (read ahead by the walk), copied from
-  // a zero block the tree owns so the call records no memset
-  static const OpF64 kZero64[1] = {};
-  static const OpF32 kZero32[1] = {};
-  hipError_t e = hipMemcpyAsync(b + t->off_ops64 + t->ops64.size() * sizeof(OpF64), kZero64, sizeof(OpF64),
+  // the zero records after each op array (read ahead by the walk), copied
+  // from a static zero block so the call records no memset
+  static const OpF64 kZero64[kOpTail] = {};
+  static const OpF32 kZero32[kOpTail] = {};
+  hipError_t e = hipMemcpyAsync(b + t->off_ops64 + t->ops64.size() * sizeof(OpF64), kZero64, sizeof kZero64,
                                 hipMemcpyHostToDevice, st);
   if (e == hipSuccess)
-    e = hipMemcpyAsync(b + t->off_ops32 + t->ops32.size() * sizeof(OpF32), kZero32, sizeof(OpF32),
+    e = hipMemcpyAsync(b + t->off_ops32 + t->ops32.size() * sizeof(OpF32), kZero32, sizeof kZero32,
                        hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !t->ops64.empty())
     e = hipMemcpyAsync(b + t->off_ops64, t->ops64.data(), t->ops64.size() * sizeof(OpF64),

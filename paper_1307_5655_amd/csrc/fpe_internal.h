@@ -87,6 +87,9 @@ struct alignas(32) OpF32 {   // double-float walk: constants pre-split on the ho
   float pad;
 };
 static_assert(sizeof(OpF32) == 32, "OpF32 is one 32-byte scalar load");
+// zero records after each op array: the walk reads op records in pairs, up to
+// three records past END
+constexpr int kOpTail = 3;
 
 // Power chain (fast exponentiation, Section 2.2): table[dst] = x_var (LOAD)
 // or table[s1] * table[s2] (MUL), in order.  Entries 0..n_used-1 are the ones

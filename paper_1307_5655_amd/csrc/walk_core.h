@@ -613,49 +613,26 @@ struct Walker {
   // The walk: one flat loop over the ops and one switch on the op's dispatch
   // code (set by the host), whose cases carry compile-time accumulator
   // indices.
-  // Waits for the outstanding scalar load of the next op (s_waitcnt
-  // lgkmcnt(0); vmcnt and expcnt left at their maxima).  Scalar loads may
-  // return out of order, so without this wait at the end of every op the
-  // compiler would wait at the loop head, right after issuing the load.
+  // Waits for the outstanding scalar load of the next ops (s_waitcnt
+  // lgkmcnt(0); vmcnt and expcnt left at their maxima).  Without this wait
+  // after the ops that the load overlaps, the compiler would wait at the loop
+  // head, right after issuing the load.
   static __device__ __forceinline__ void settle() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
-  // The next op's scalar load is issued before this op runs and settled
-  // after it, so its latency overlaps this op's dispatch and arithmetic (the
-  // op arrays end with one zero record after END, so the load past END stays
-  // in bounds).
-  __device__ __forceinline__ void walk() {
-    // the op array is read-only while a kernel runs: reading it through the
-    // constant address space keeps its loads scalar whatever the kernel
-    // stores or waits on
-    using CW = const __attribute__((address_space(4))) uint64_t;
-    CW* __restrict__ op = (CW*)ops;
-    static_assert(sizeof(Op) == 4 * sizeof(uint64_t), "op records are 32 bytes");
-    auto fetch = [](CW* p) {
-      uint64_t w[4] = {p[0], p[1], p[2], p[3]};
-      Op r;
-      __builtin_memcpy(&r, w, sizeof r);
-      return r;
-    };
-    Op next = fetch(op);
-    settle();
-#pragma unroll 1
-    for (;;) {
-      const Op o = next;
-      op += 4;
-      next = fetch(op);
-      if constexpr (DMAX <= 2) {
-        // chain-like walks (Hörner): almost every op is NODE_OPEN at depth 1
-        // with the first register power; test it before the switch
-        constexpr uint32_t kHot = make_code(1, kNodeOpen, 0);
-        if (op_code(o.deg) == kHot) {
-          step<kHot>(o);
-          settle();
-          continue;
-        }
+  // One op; true at END.
+  __device__ __forceinline__ bool run_op(const Op& o) {
+    if constexpr (DMAX <= 2) {
+      // chain-like walks (Hörner): almost every op is NODE_OPEN at depth 1
+      // with the first register power; test it before the switch
+      constexpr uint32_t kHot = make_code(1, kNodeOpen, 0);
+      if (op_code(o.deg) == kHot) {
+        step<kHot>(o);
+        return false;
       }
-      switch (op_code(o.deg)) {
+    }
+    switch (op_code(o.deg)) {
 #define FPE_END(c) \
-  case c: finish<((c) >> 6)>(o); return;
+  case c: finish<((c) >> 6)>(o); return true;
 #define FPE_OP(c)                                                          \
   case c:                                                                  \
     if constexpr (((c) & 15) <= DMAX) step<(c)>(o);                        \
@@ -674,15 +651,66 @@ struct Walker {
   FPE_OP(16 + 64 * (p)) FPE_L(1, p)                                        \
   FPE_OP(32 + 64 * (p)) FPE_L(2, p)                                        \
   FPE_OP(48 + 64 * (p)) FPE_L(3, p)
-        FPE_P(0) FPE_P(1) FPE_P(2) FPE_P(3) FPE_P(4) FPE_P(5)
+      FPE_P(0) FPE_P(1) FPE_P(2) FPE_P(3) FPE_P(4) FPE_P(5)
 #undef FPE_P
 #undef FPE_L
 #undef FPE_OP
 #undef FPE_END
-        default:
-          break;
-      }
+      default:
+        break;
+    }
+    return false;
+  }
+
+  // The next op record is loaded before the current op runs and settled
+  // after it, so the load's latency overlaps the op's dispatch and
+  // arithmetic.  Scalar loads may return out of order, so only a full wait is
+  // safe and one load is outstanding at a time.  The FP64 walk, whose ops
+  // carry one fused multiply-add per point, runs the ops in pairs: the two
+  // records of the next pair come in one 64-byte load, which then has two
+  // ops of arithmetic to arrive (measured 7-23 % faster).  The walks with
+  // more arithmetic per op (compensated, double-double, mod p) were measured
+  // slower in pairs (a second copy of the switch, more registers) and run
+  // single ops.  The op arrays end with kOpTail zero records after END, so
+  // the loads past END stay in bounds.
+  static constexpr bool kPairs = std::is_same_v<Ar, ArF64>;
+  __device__ __forceinline__ void walk() {
+    // the op array is read-only while a kernel runs: reading it through the
+    // constant address space keeps its loads scalar whatever the kernel
+    // stores or waits on
+    using CW = const __attribute__((address_space(4))) uint64_t;
+    CW* __restrict__ op = (CW*)ops;
+    static_assert(sizeof(Op) == 4 * sizeof(uint64_t), "op records are 32 bytes");
+    auto fetch = [](CW* p) {
+      uint64_t w[4] = {p[0], p[1], p[2], p[3]};
+      Op r;
+      __builtin_memcpy(&r, w, sizeof r);
+      return r;
+    };
+    if constexpr (kPairs) {
+      Op a = fetch(op), b = fetch(op + 4);
       settle();
+#pragma unroll 1
+      for (;;) {
+        const Op o0 = a, o1 = b;
+        op += 8;
+        a = fetch(op);
+        b = fetch(op + 4);
+        if (run_op(o0)) return;
+        if (run_op(o1)) return;
+        settle();
+      }
+    } else {
+      Op next = fetch(op);
+      settle();
+#pragma unroll 1
+      for (;;) {
+        const Op o = next;
+        op += 4;
+        next = fetch(op);
+        if (run_op(o)) return;
+        settle();
+      }
     }
   }
 #undef FPE_FOR_J
