@@ -18,6 +18,9 @@ Workloads (all synthetic; the paper measures on no public dataset):
                     1e6 points uniform in (Z/pZ)^3.
 * ``compose``       4096 instances of p (degree 255) and q (degree 15), all
                     coefficients uniform in [0, 2^31 - 2].
+* ``interval``      boxes around the points of the workloads above: each
+                    interval has a width drawn from {0, 2^-20, 2^-8, 0.25} and
+                    holds its point at a uniform position (``interval_boxes``).
 * ``served``        a Poisson stream of evaluate requests with 1-3 variables,
                     10-10,000 terms (log-uniform), 1e3-1e6 points (log-uniform)
                     in the unit box [-1, 1]^v and a scheme in {H, E, B}.
@@ -162,6 +165,19 @@ def compose_batch(batch: int = 4096, dp: int = 255, dq: int = 15, seed_k: int = 
 # ----------------------------------------------------------------------------
 # multivariate FP64 (served) polynomials
 # ----------------------------------------------------------------------------
+
+def interval_boxes(points: np.ndarray, g: np.random.Generator,
+                   widths=(0.0, 2.0 ** -20, 2.0 ** -8, 0.25)) -> np.ndarray:
+    """Intervals (lo, hi) around ``points`` (any shape): a width w drawn
+    uniformly from ``widths`` per point and a position u ~ U[0, 1], lo = x - u w,
+    hi = x + (1 - u) w.  Returns float64 [..., 2]."""
+    x = np.asarray(points, dtype=np.float64)
+    w = np.asarray(widths, dtype=np.float64)[g.integers(0, len(widths), size=x.shape)]
+    u = g.uniform(0.0, 1.0, size=x.shape)
+    lo = x - u * w
+    hi = x + (1.0 - u) * w
+    return np.ascontiguousarray(np.stack([lo, hi], axis=-1))
+
 
 @dataclass
 class MultiInput:

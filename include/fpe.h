@@ -56,7 +56,9 @@ const char* fpe_version(void);
 typedef enum {
   FPE_F64 = 0,   /* plain FP64 walk, one fused multiply-add per node (Section 2.1) */
   FPE_F32C = 1,  /* compensated FP32 (double-float) walk + FP64 fallback */
-  FPE_MODP = 2   /* exact walk in Z/pZ, p = 2^61 - 1 for evaluation, 2^31 - 1 for composition */
+  FPE_MODP = 2,  /* exact walk in Z/pZ, p = 2^61 - 1 for evaluation, 2^31 - 1 for composition */
+  FPE_IVAL = 3   /* interval walk (the abstract's interval coefficient type): FP64 bounds
+                    rounded outward, enclosing the tree's interval evaluation over a box */
 } fpe_domain;
 
 /* Function schemes (Section 1.1 and 1.2).  The argument of f is the degree n
@@ -108,7 +110,8 @@ typedef struct fpe_tree fpe_tree;
  *   nvars   1..8
  *   nterms  >= 1 terms; exponents >= 0 and < 2^20; no monomial twice.
  *           Terms with a zero coefficient are dropped (all zero: FPE_EINVAL).
- *   coeffs  host array: double[nterms] for FPE_F64 / FPE_F32C (finite), or
+ *   coeffs  host array: double[nterms] for FPE_F64 / FPE_F32C / FPE_IVAL (finite;
+ *           FPE_IVAL takes them as exact point coefficients), or
  *           uint64_t[batch * nterms] residues < modulus for FPE_MODP (row r
  *           holds instance r; all rows share the exponents; the tree shape is
  *           taken from the union of nonzero positions).
@@ -178,9 +181,16 @@ size_t fpe_workspace_bytes(const fpe_tree* t, int64_t npts);
 
 /* Evaluate the uploaded tree at npts points.
  *   pts  host array of nvars device pointers, each to npts values (SoA):
- *        double for FPE_F64 / FPE_F32C, uint64_t residues < p for FPE_MODP.
- *   out  device array of npts doubles (FPE_F64, FPE_F32C) or uint64_t (FPE_MODP).
- *   opts may be NULL for FPE_F64 / FPE_MODP.
+ *        double for FPE_F64 / FPE_F32C, uint64_t residues < p for FPE_MODP;
+ *        for FPE_IVAL each points to double[2 * npts], interval i of that
+ *        variable as (lo, hi) at [2i], [2i + 1], lo <= hi.
+ *   out  device array of npts doubles (FPE_F64, FPE_F32C) or uint64_t (FPE_MODP);
+ *        FPE_IVAL: double[2 * npts], (lo, hi) per point.  [lo, hi] contains the
+ *        interval evaluation of the tree over the box (exact interval sums and
+ *        products, each power x^d taken as its exact range over the interval),
+ *        hence p(x) for every x in the box; every bound is rounded outward.
+ *        A bound that overflows is returned as [-inf, +inf].
+ *   opts may be NULL for FPE_F64 / FPE_MODP / FPE_IVAL.
  * Errors: FPE_EINVAL (not uploaded, npts < 0, NULL pointers), FPE_ENOMEM
  * (workspace too small), FPE_EUNSUPPORTED (walk deeper than the kernels hold),
  * FPE_EDEVICE. */

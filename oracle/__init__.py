@@ -15,6 +15,8 @@ Contents (each function cites the passage of the paper it follows):
 * ``exact``    the plain definition p(x) = sum c_m x^m: exact rationals,
                exact residues mod p, double-double Hörner, fsum closed forms.
 * ``compose``  exact composition p(q(x)) over Z/pZ by schoolbook expansion.
+* ``interval`` the tree's value over a box with exact interval operations
+               (the interval coefficient type of the Abstract).
 * ``native``   the same definitions in plain C for full-size samples and for
                the timed CPU baseline (built by ``oracle/build_native.sh``).
 

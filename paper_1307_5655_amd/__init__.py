@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfpe.so")
 
-F64, F32C, MODP = 0, 1, 2
+F64, F32C, MODP, IVAL = 0, 1, 2, 3
 DIRECT, HORNER, ESTRIN, BALANCED, BALANCED_FLOOR, THRESHOLD, TABLE = range(7)
 SCHEMES = {"direct": DIRECT, "horner": HORNER, "estrin": ESTRIN, "balanced": BALANCED,
            "balanced_floor": BALANCED_FLOOR, "threshold": THRESHOLD, "table": TABLE}
@@ -253,16 +253,19 @@ def workspace_bytes(tree: Tree, npts: int) -> int:
 def evaluate(tree: Tree, pts, out=None, tol: float = 1e-12, force: int = 0, cond_out=None,
              flags_out=None, workspace=None, nfallback_out=None, stream=None, events=None,
              points_per_lane: int = 0):
-    """Evaluate ``tree`` at device points ``pts`` (list of 1-D tensors, one per
-    variable; float64, or uint64 residues stored as int64 for FPE_MODP)."""
+    """Evaluate ``tree`` at device points ``pts`` (list of tensors, one per
+    variable: 1-D float64, or uint64 residues stored as int64 for FPE_MODP;
+    for FPE_IVAL [npts, 2] float64 intervals (lo, hi), and the result is
+    [npts, 2] enclosures)."""
     import torch
     if tree._dev is None:
         raise FpeError(-1, "tree is not uploaded")
     pts = list(pts) if isinstance(pts, (list, tuple)) else [pts]
-    npts = pts[0].numel()
+    npts = pts[0].shape[0] if tree.domain == IVAL else pts[0].numel()
     if out is None:
         dt = torch.int64 if tree.domain == MODP else torch.float64
-        out = torch.empty(npts, dtype=dt, device=pts[0].device)
+        shape = (npts, 2) if tree.domain == IVAL else (npts,)
+        out = torch.empty(shape, dtype=dt, device=pts[0].device)
     arr = (ctypes.c_void_p * 8)(*[p.data_ptr() for p in pts])
     opts = EvalOpts(tol, force, points_per_lane, cond_out.data_ptr() if cond_out is not None else None,
                     flags_out.data_ptr() if flags_out is not None else None, None, 0,

@@ -244,8 +244,9 @@ fpe_status fpe_tree_deserialize(const void* buf, size_t bytes, fpe_tree** out) {
     return fail(FPE_EINVAL, "corrupt serialised tree");
   }
   for (const auto& c : t->chain)
-    if (c.dst >= t->n_table || (c.kind == kChainMul && (c.s1 >= t->n_table || c.s2 >= t->n_table)) ||
-        (c.kind == kChainLoad && c.s1 >= t->nvars)) {
+    if (c.dst >= t->n_table ||
+        (chain_is_mul(c.kind) && (c.s1 >= t->n_table || c.s2 >= t->n_table || chain_var(c.kind) >= (uint32_t)t->nvars)) ||
+        (!chain_is_mul(c.kind) && (c.kind != kChainLoad || c.s1 >= t->nvars))) {
       delete t;
       return fail(FPE_EINVAL, "corrupt serialised tree (power chain)");
     }

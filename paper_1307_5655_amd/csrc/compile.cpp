@@ -339,7 +339,7 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
   if (nvars < 1 || nvars > 8) return fail(FPE_EINVAL, "nvars must be in 1..8");
   if (nterms < 1) return fail(FPE_EINVAL, "nterms must be >= 1");
   if (!exps || !coeffs || !fs) return fail(FPE_EINVAL, "NULL exps, coeffs or scheme");
-  if (domain != FPE_F64 && domain != FPE_F32C && domain != FPE_MODP)
+  if (domain != FPE_F64 && domain != FPE_F32C && domain != FPE_MODP && domain != FPE_IVAL)
     return fail(FPE_EINVAL, "unknown domain");
   if (batch < 1) return fail(FPE_EINVAL, "batch must be >= 1");
   if (domain != FPE_MODP && batch != 1) return fail(FPE_EINVAL, "batch > 1 needs FPE_MODP");
@@ -536,11 +536,15 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
   // 32, 48 entries is taken that covers every power with at most 1 in 64
   // walk steps reading a product.  A batch tree (composition) keeps its coefficients per
   // instance, so its ops carry node indices instead of coefficient values,
-  // and its table may hold up to 48 entries without products.
+  // and its table may hold up to 48 entries without products.  So does an
+  // interval tree: the product of two power enclosures is wider than the
+  // range of the power when the interval contains 0, so its powers come only
+  // from the table or, beyond it, are computed on the fly from the bounds.
   const bool index_ops = domain == FPE_MODP && modulus == kP31;
-  const int32_t cap = index_ops ? kMaxTable : kTableCap;
+  const bool no_products = index_ops || domain == FPE_IVAL;
+  const int32_t cap = no_products ? kMaxTable : kTableCap;
   PowerPlan plan;
-  if (index_ops) {
+  if (no_products) {
     for (size_t k = 0; k < byf.size(); ++k) {
       PowerPlan tmp = plan;
       tmp.ensure(byf[k].second.first, byf[k].second.second, cap);
@@ -589,13 +593,15 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
     if (s.kind == kChainMul) {
       c.s1 = (uint8_t)rank[s.s1];
       c.s2 = (uint8_t)rank[s.s2];
+      const auto& en = plan.entries[s.dst];
+      c.kind = (uint8_t)(kChainMul | ((en.second & 1) ? kChainOdd : 0u) | ((uint32_t)en.first << 4));
     }
     t->chain.push_back(c);
   }
   // pending powers: the product of two (or three) table entries of the same
   // variable
   std::map<std::pair<int32_t, int32_t>, std::array<uint32_t, 3>> pairs;
-  if (!index_ops) {
+  if (!no_products) {
     auto find = [&](int32_t v, int32_t d) -> int32_t {
       auto it = plan.index.find({v, d});
       return it == plan.index.end() ? -1 : rank[it->second];

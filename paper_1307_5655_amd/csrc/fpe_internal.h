@@ -95,6 +95,12 @@ constexpr int kOpTail = 3;
 // or table[s1] * table[s2] (MUL), in order.  Entries 0..n_used-1 are the ones
 // the walk reads, sorted by how often it reads them.
 enum ChainKind : uint32_t { kChainLoad = 0, kChainMul = 1 };
+// A MUL step's kind also carries its entry's variable (bits 4-7) and whether
+// the entry's degree is odd (bit 1), for the interval walk, which takes the
+// range of x^d from the bounds of |lo|^d and |hi|^d; LOAD steps stay 0.
+constexpr uint32_t kChainOdd = 2;
+__host__ __device__ inline bool chain_is_mul(uint32_t kind) { return (kind & 1u) != 0; }
+__host__ __device__ inline uint32_t chain_var(uint32_t kind) { return kind >> 4; }
 struct ChainStep {
   uint8_t kind, dst, s1, s2;
 };
@@ -233,6 +239,7 @@ struct KernelLaunch {
 struct F32COut;
 void launch_f64(const KernelLaunch& L, double* out);
 void launch_m61(const KernelLaunch& L, uint64_t* out);
+void launch_iv(const KernelLaunch& L, double* out);
 void launch_df32(const KernelLaunch& L, const F32COut& o);
 void launch_fallback(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out);
 }  // namespace fpe

@@ -20,7 +20,7 @@ namespace {
 // amortises the wave-uniform dispatch; tables beyond kTableCapMulti entries
 // and trees with on-the-fly powers use the one-point kernels.
 int pick_ppl(const fpe_tree* t, const fpe_eval_opts* opts) {
-  if (t->n_offtable > 0 || t->n_table > kTableCapMulti) return 1;
+  if (t->n_offtable > 0 || t->n_table > kTableCapMulti || t->domain == FPE_IVAL) return 1;
   // Default: 4 points per lane for FP64, 2 otherwise (measured best on
   // MI355X for both chain-like and deep walks once the power table lives in
   // private memory); walks deeper than 8 hold twice the accumulators and take
@@ -51,6 +51,14 @@ fpe_status launch_eval(const fpe_tree* t, const void* const* pts, int64_t npts, 
   if (t->domain == FPE_F64) {
     if (eb) (void)hipEventRecord(eb, st);
     launch_f64(L, (double*)out);
+    if (ee) (void)hipEventRecord(ee, st);
+  } else if (t->domain == FPE_IVAL) {
+    // intervals are read and written as 16-byte (lo, hi) pairs
+    for (int j = 0; j < t->nvars; ++j)
+      if (((uintptr_t)pts[j]) & 15) return fail(FPE_EINVAL, "interval point arrays must be 16-byte aligned");
+    if (((uintptr_t)out) & 15) return fail(FPE_EINVAL, "interval output must be 16-byte aligned");
+    if (eb) (void)hipEventRecord(eb, st);
+    launch_iv(L, (double*)out);
     if (ee) (void)hipEventRecord(ee, st);
   } else if (t->domain == FPE_MODP) {
     if (t->modulus != kP61) return fail(FPE_EUNSUPPORTED, "evaluation modulus must be 2^61-1");

@@ -16,7 +16,8 @@
 //         floats, a running error bound and the condition sum
 //         ptilde(|x|) = sum |c_m| |x|^m in FP32; the result hi + lo in FP64;
 //   DD64  double-double (TwoProd by FP64 fma): the fallback re-evaluation;
-//   M61   exact arithmetic modulo the Mersenne prime 2^61 - 1.
+//   M61   exact arithmetic modulo the Mersenne prime 2^61 - 1;
+//   IV    FP64 intervals rounded outward (point coefficients, interval points).
 #pragma once
 #include <hip/hip_runtime.h>
 
@@ -306,6 +307,95 @@ struct ArDF32 {
   }
 };
 
+// Interval walk.  A value is an interval [lo, hi] of FP64 numbers; the
+// coefficients are exact points.  Every bound comes from one
+// round-to-nearest operation r (a product, an fma or a sum) and is then moved
+// outward: dn(r) = RN(RN(r - |r| 2^-52) - 2^-1074) <= exact <= up(r).  For a
+// normal r, |r| 2^-52 is at least one unit in the last place of r, twice the
+// worst round-to-nearest error, and subtracting it rounds to a float at or
+// below r - ulp; the 2^-1074 term covers results at or below the subnormal
+// range.  A bound that overflows turns the point's result into
+// [-inf, +inf] (see iv_finish).
+struct IV {
+  double lo, hi;
+};
+__device__ __forceinline__ double iv_dn(double r) {
+  return __builtin_fma(-__builtin_fabs(r), 0x1p-52, r) - 0x1p-1074;
+}
+__device__ __forceinline__ double iv_up(double r) {
+  return __builtin_fma(__builtin_fabs(r), 0x1p-52, r) + 0x1p-1074;
+}
+// a * X + [bl, bh] for a point a: the ends of a X are a times the ends of X,
+// swapped when a < 0 (a is wave-uniform, so the choice is a select).
+__device__ __forceinline__ IV iv_axb(double a, const IV& X, double bl, double bh) {
+  const bool neg = a < 0.0;
+  const double xl = neg ? X.hi : X.lo, xh = neg ? X.lo : X.hi;
+  return IV{iv_dn(__builtin_fma(a, xl, bl)), iv_up(__builtin_fma(a, xh, bh))};
+}
+// U * X + [bl, bh]: the product's ends are the least and greatest of the four
+// end products; each is fused with the matching end of b, and rounding outward
+// after the min / max keeps the bound (dn and up are monotone).
+__device__ __forceinline__ IV iv_mad(const IV& U, const IV& X, double bl, double bh) {
+  const double l1 = __builtin_fma(U.lo, X.lo, bl), l2 = __builtin_fma(U.lo, X.hi, bl);
+  const double l3 = __builtin_fma(U.hi, X.lo, bl), l4 = __builtin_fma(U.hi, X.hi, bl);
+  const double h1 = __builtin_fma(U.lo, X.lo, bh), h2 = __builtin_fma(U.lo, X.hi, bh);
+  const double h3 = __builtin_fma(U.hi, X.lo, bh), h4 = __builtin_fma(U.hi, X.hi, bh);
+  return IV{iv_dn(fmin(fmin(l1, l2), fmin(l3, l4))), iv_up(fmax(fmax(h1, h2), fmax(h3, h4)))};
+}
+// Bounds [lo, hi] on m^d for m >= 0 from bounds on m^a and m^b, a + b = d.
+__device__ __forceinline__ IV mag_mul(const IV& a, const IV& b) {
+  return IV{fmax(iv_dn(a.lo * b.lo), 0.0), iv_up(a.hi * b.hi)};
+}
+// The range of x^d over X = [l, h] from bounds ml on |l|^d and mh on |h|^d:
+// odd d is increasing; even d is decreasing below 0 and increasing above, with
+// its least value 0 when 0 lies in X.
+__device__ __forceinline__ IV power_range(const IV& X, const IV& ml, const IV& mh, bool odd) {
+  if (odd) return IV{X.lo >= 0.0 ? ml.lo : -ml.hi, X.hi >= 0.0 ? mh.hi : -mh.lo};
+  if (X.lo >= 0.0) return IV{ml.lo, mh.hi};
+  if (X.hi <= 0.0) return IV{mh.lo, ml.hi};
+  return IV{0.0, fmax(ml.hi, mh.hi)};
+}
+// Bounds on m^d by binary exponentiation (powers outside the table).
+__device__ __forceinline__ IV mag_pow(double m, uint32_t d) {
+  IV r{1.0, 1.0}, b{m, m};
+  for (; d; d >>= 1) {
+    if (d & 1u) r = mag_mul(r, b);
+    b = mag_mul(b, b);
+  }
+  return r;
+}
+
+struct ArIV {
+  using Op = OpF64;
+  using Acc = IV;
+  using Pow = IV;
+  using In = IV;
+  static __device__ __forceinline__ const Op* ops(const DevTree& t) { return t.ops64; }
+  static __device__ __forceinline__ Acc fma_ca(const Op& o, const Pow& X, const Acc& top) {
+    return iv_axb(u2d(o.a), X, top.lo, top.hi);
+  }
+  static __device__ __forceinline__ Acc fma_tb(const Acc& top, const Pow& X, const Op& o) {
+    const double b = u2d(o.b);
+    return iv_mad(top, X, b, b);
+  }
+  static __device__ __forceinline__ Acc fma_ab(const Op& o, const Pow& X) {
+    const double b = u2d(o.b);
+    return iv_axb(u2d(o.a), X, b, b);
+  }
+  static __device__ __forceinline__ Acc fma_tt(const Acc& top, const Pow& X, const Acc& below) {
+    return iv_mad(top, X, below.lo, below.hi);
+  }
+  static __device__ __forceinline__ Acc leaf_root(const Op& o) { return IV{u2d(o.a), u2d(o.a)}; }
+  static __device__ __forceinline__ Acc mul(const Acc& a, const Pow& X) { return iv_mad(a, X, 0.0, 0.0); }
+  static __device__ __forceinline__ Pow off_table(const In& xv, const Op& o) {
+    const uint32_t d = op_deg(o.deg);
+    return power_range(xv, mag_pow(__builtin_fabs(xv.lo), d), mag_pow(__builtin_fabs(xv.hi), d), (d & 1u) != 0);
+  }
+  // interval trees are compiled without power products; this product of two
+  // enclosures is still an enclosure
+  static __device__ __forceinline__ Pow pair(const Pow& a, const Pow& b) { return iv_mad(a, b, 0.0, 0.0); }
+};
+
 // ----------------------------------------------------------------------------
 // power tables
 // ----------------------------------------------------------------------------
@@ -430,6 +520,36 @@ struct TabP3 {
   __device__ __forceinline__ P3 get(uint32_t i) const { return pm[i]; }
 };
 
+// Interval tables: the chain runs on bounds of |l|^d and |h|^d (l, h the ends
+// of the entry's variable), and each entry's enclosure of the range of x^d is
+// formed from them as the step that makes it runs (a MUL step's kind carries
+// the entry's variable and the parity of its degree).
+template <int CAP>
+struct TabIV {
+  IV pm[CAP];             // entry i: enclosure of the range of x_var^d (private)
+  IV ml[CAP], mh[CAP];    // bounds on |l|^d and |h|^d
+  __device__ __forceinline__ void build(const DevTree& tr, const IV* x, RegPow<IV>& rp) {
+    for (int c = 0; c < tr.n_chain; ++c) {
+      const ChainStep st = tr.chain[c];
+      if (!chain_is_mul(st.kind)) {
+        const IV X = coord(x, st.s1);
+        const double l = __builtin_fabs(X.lo), h = __builtin_fabs(X.hi);
+        ml[st.dst] = IV{l, l};
+        mh[st.dst] = IV{h, h};
+        pm[st.dst] = X;
+      } else {
+        const IV a = mag_mul(ml[st.s1], ml[st.s2]), b = mag_mul(mh[st.s1], mh[st.s2]);
+        ml[st.dst] = a;
+        mh[st.dst] = b;
+        pm[st.dst] = power_range(coord(x, chain_var(st.kind)), a, b, (st.kind & kChainOdd) != 0);
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? pm[k] : IV{0.0, 0.0};
+  }
+  __device__ __forceinline__ IV get(uint32_t i) const { return pm[i]; }
+};
+
 // LDS tier of the tables: entries kRegPowers .. kRegPowers+kLdsPowers-1 (the
 // next most used after the register copies) of every point of a wavefront,
 // stored as 32-bit planes [entry][word][point j][lane] so a wavefront reads 64
@@ -482,6 +602,7 @@ template <int CAP> struct TabFor<ArF64, CAP> { using T = TabF64<CAP>; };
 template <int CAP> struct TabFor<ArDD, CAP> { using T = TabDD<CAP>; };
 template <int CAP> struct TabFor<ArM61, CAP> { using T = TabM61<CAP>; };
 template <int CAP> struct TabFor<ArDF32, CAP> { using T = TabP3<CAP>; };
+template <int CAP> struct TabFor<ArIV, CAP> { using T = TabIV<CAP>; };
 template <int PPL> constexpr int table_cap() { return PPL > 1 ? kTableCapMulti : kMaxTable; }
 
 // ----------------------------------------------------------------------------

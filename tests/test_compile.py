@@ -207,3 +207,22 @@ def test_package_binds_to_one_hip_runtime():
     r = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, r.stderr
     assert r.stdout.strip().splitlines()[-1] == "1"
+
+
+@pytest.mark.parametrize("scheme", ["horner", "estrin", "balanced", "direct"])
+def test_interval_trees_share_the_shape_and_take_no_power_products(scheme):
+    """An interval tree has the FP64 tree's nodes; its powers come from the
+    table or are computed on the fly, never as products of two entries, and
+    every MUL step of its chain names its variable and degree parity."""
+    g = np.random.default_rng(5)
+    c = g.uniform(-1, 1, 700)
+    c[g.choice(699, 70, replace=False)] = 0.0
+    e = np.nonzero(c)[0].astype(np.int32).reshape(-1, 1)
+    t64 = fpe.Tree(e, c[e[:, 0]], scheme, fpe.F64)
+    tiv = fpe.Tree(e, c[e[:, 0]], scheme, fpe.IVAL)
+    assert np.array_equal(t64.nodes(), tiv.nodes())
+    assert tiv.info.n_pair_ops == 0
+    assert tiv.info.walk_depth == t64.info.walk_depth
+    assert tiv.info.n_table <= 48
+    back = fpe.Tree.deserialize(tiv.serialize())
+    assert np.array_equal(back.nodes(), tiv.nodes())
