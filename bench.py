@@ -197,6 +197,45 @@ def modp_phase(fpe, fpe_inputs, torch, dev, hev, reps: int = 3):
     return res
 
 
+# FP64 operations of one interval step (bounds rounded outward: one fma or
+# product, then two operations per bound to move it out): LEAF_ADD a X + top
+# and LEAF_OPEN a X + b take 2 fma + 4; NODE_OPEN top X + b takes 4 end
+# products fused with b, 3 min, 3 max and 4; NODE_ADD top X + below 8 fused
+# end products, 6 min / max and 4.
+IVAL_OPS_BY_KIND = (6, 14, 6, 18, 0)
+
+
+def interval_phase(fpe, fpe_inputs, torch, dev, hev, npts: int, reps: int = 3):
+    """Interval enclosures over boxes around the sparse univariate points
+    (degrees 3000 and 5000, widths {0, 2^-20, 2^-8, 0.25})."""
+    res = {}
+    ops = secs = 0.0
+    for n in (3000, 5000):
+        inp = fpe_inputs.sparse_uni(n, npts=npts)
+        e, c = inp.terms()
+        box = torch.from_numpy(fpe_inputs.interval_boxes(inp.points, fpe_inputs.rng_for(6, n))).to(dev)
+        out = torch.empty((npts, 2), dtype=torch.float64, device=dev)
+        for s in ("balanced", "estrin", "horner"):
+            t = fpe.Tree(e, c, s, fpe.IVAL).upload(dev)
+            fpe.evaluate(t, [box], out=out)
+            ms = []
+            for _ in range(reps):
+                e0, e1 = hev.create(), hev.create()
+                fpe.evaluate(t, [box], out=out, events=(e0, e1))
+                torch.cuda.synchronize()
+                ms.append(hev.elapsed_ms(e0, e1))
+            m = float(np.median(ms))
+            k_ops = float(sum(k * o for k, o in zip(t.info.n_ops_kind, IVAL_OPS_BY_KIND))) * npts
+            ops += k_ops
+            secs += m * 1e-3
+            res[f"n{n}_{s}"] = {"walk_ms": m, "term_evals_per_s": float(t.info.n_terms) * npts / (m * 1e-3)}
+        del box, out
+    res["roofline"] = {"kernel": "k_eval_iv (interval walk)", "bound": "alu",
+                       "achieved": ops / secs / 1e12, "peak": FP64_FMA_PEAK / 1e12,
+                       "unit": "T FP64 VALU lane-ops/s", "frac": ops / secs / FP64_FMA_PEAK}
+    return res
+
+
 def compose_phase(fpe, fpe_inputs, torch, dev, reps: int = 3):
     """4096 instances of p(q(x)) mod 2^31-1, deg p = 255, deg q = 15."""
     inp = fpe_inputs.compose_batch()
@@ -378,7 +417,7 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
-    served = latency = modp = compose = None
+    served = latency = modp = compose = ival = None
     if not args.no_extra:
         log("served stream")
         served, latency = served_phase(fpe, fpe_inputs, torch, dev, args.served_requests, load=0.8)
@@ -386,6 +425,8 @@ def main():
         modp = modp_phase(fpe, fpe_inputs, torch, dev, hev)
         log("composition")
         compose = compose_phase(fpe, fpe_inputs, torch, dev)
+        log("interval")
+        ival = interval_phase(fpe, fpe_inputs, torch, dev, hev, args.points)
 
     cpu = None
     if not args.no_cpu:
@@ -438,6 +479,7 @@ def main():
         "served": None if served is None else {"saturation": served, "poisson": latency},
         "modp_trivariate": modp,
         "compose_4096": compose,
+        "interval_1e7": ival,
     }
     print(json.dumps(out), flush=True)
 
