@@ -37,18 +37,18 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK = 256 * 128 * 2.4e9
 FP64_FMA_PEAK = 256 * 64 * 2.4e9
-# FP32 operations of one compensated multiply-add a * X + b: product and its
-# error by fma (2), three cross terms (3), TwoSum (6), two low-order adds (2),
-# FastTwoSum (3), then the running error bound: e_a |X| + e_b (1 fma, when
-# the product's operand is an accumulator), 20 u^2 |p| (1 fma) and 6 u^2 |b|
-# (1 fma when b is an accumulator; a coefficient's term is a constant of the
-# op).  Per step kind: LEAF_ADD a X + top 18, NODE_OPEN top X + b 18,
-# LEAF_OPEN a X + b 17, NODE_ADD top X + below 19; END (once per point) is not
-# counted.  The condition sum (1 more fma) is computed only when per-point
+# FP32 operations of one compensated multiply-add a * X + b (X read as two
+# floats): product and its error by fma (2), two cross terms (2), TwoSum (6),
+# two low-order adds (2), FastTwoSum (3), then the running error bound:
+# e_a |X| + e_b (1 fma, when the product's operand is an accumulator),
+# 20 u^2 |p| (1 fma) and 6 u^2 |b| (1 fma when b is an accumulator; a
+# coefficient's term is a constant of the op).  Per step kind: LEAF_ADD
+# a X + top 17, NODE_OPEN top X + b 17, LEAF_OPEN a X + b 16, NODE_ADD
+# top X + below 18; END (once per point) is not counted.  The condition sum (1 more fma) is computed only when per-point
 # condition numbers are requested, which the timed step does not do (the
 # condition numbers of the workload are reported from the oracle's sample
 # instead).
-DF32_OPS_BY_KIND = (18, 18, 17, 19, 0)
+DF32_OPS_BY_KIND = (17, 17, 16, 18, 0)
 
 
 def log(msg):

@@ -121,6 +121,8 @@ struct ArF64 {
   using Acc = double;
   using Pow = double;
   using In = double;
+  using Full = Pow;
+  static __device__ __forceinline__ Pow to_pow(const Pow& f) { return f; }
   static __device__ __forceinline__ const Op* ops(const DevTree& t) { return t.ops64; }
   static __device__ __forceinline__ Acc fma_ca(const Op& o, Pow X, Acc top) {   // a*X + top
     return __builtin_fma(u2d(o.a), X, top);
@@ -145,6 +147,8 @@ struct ArDD {   // double-double walk (fallback), double-double powers
   using Acc = DD;
   using Pow = DD;
   using In = double;
+  using Full = Pow;
+  static __device__ __forceinline__ Pow to_pow(const Pow& f) { return f; }
   static __device__ __forceinline__ const Op* ops(const DevTree& t) { return t.ops64; }
   static __device__ __forceinline__ Acc fma_ca(const Op& o, const Pow& X, const Acc& top) {
     return dd_fma(DD{u2d(o.a), 0.0}, X, top);
@@ -177,6 +181,8 @@ struct ArM61 {
   using Acc = uint64_t;
   using Pow = uint64_t;
   using In = uint64_t;
+  using Full = Pow;
+  static __device__ __forceinline__ Pow to_pow(const Pow& f) { return f; }
   static __device__ __forceinline__ const Op* ops(const DevTree& t) { return t.ops64; }
   static __device__ __forceinline__ Acc fma_ca(const Op& o, Pow X, Acc top) {
     return m61_add(m61_mul(o.a, X), top);
@@ -200,16 +206,18 @@ struct ArM61 {
 // walk carries e, a bound on |value - exact value of the subtree|, and t,
 // the subtree's sum of |c| |x|^m (for the condition number).
 //
-// One step a * X + b with X = X.h + X.m + X.l (a power split into three
-// floats, accurate to about 2^-70):
+// One step a * X + b with X = X.h + X.m (a power rounded to two floats,
+// within u^2 |X| of the exact power, u = 2^-24: the table keeps each power
+// to about 2^-70 and the walk reads its two leading floats):
 //   p  = fl(a.h X.h), pe = a.h X.h - p exactly (fma),
-//   pe += a.h X.m + a.l X.h + a.h X.l        (three fmas, a.l X.m dropped)
+//   pe += a.h X.m + a.l X.h                  (two fmas, a.l X.m dropped)
 //   (s, se) = TwoSum(p, b.h),  se += pe + b.l,  (hi, lo) = FastTwoSum(s, se).
-// With u = 2^-24: |pe| <= 3u|p| along the way, so the three fma roundings
-// add at most 8u^2|p|; the dropped term u^2|p|; pe + b.l and the final sum
-// round by at most u^2 (7|p| + 3|b|); the 48-bit constants a and b add
-// u^2 (|p| + |b|).  The new error is therefore at most u^2 (17|p| + 4|b|);
-// the bound uses 20 and 6 for margin, and inherited errors propagate as
+// |pe| <= 3u|p| along the way, so the fma roundings add at most 8u^2|p|; the
+// dropped term u^2|p|; the power's rounding to two floats u^2|p|; pe + b.l
+// and the final sum round by at most u^2 (7|p| + 3|b|); the 48-bit
+// constants a and b add u^2 (|p| + |b|).  The new error is therefore at most
+// u^2 (18|p| + 4|b|); the bound uses 20 and 6 for margin, and inherited
+// errors propagate as
 // e_a |X| + e_b.  When b is a coefficient (exact), the host stores 6 u^2 |b.h|
 // rounded up in the op, so that term costs nothing on the device.
 // The bound is evaluated in FP32 with |X.h| in place of |X|
@@ -222,8 +230,11 @@ struct ArM61 {
 struct DF {
   float h, l, e, t;
 };
-struct P3 {
+struct P3 {   // a table power to about 2^-70: h + m + l
   float h, m, l;
+};
+struct P2 {   // the power as the walk reads it: h + m
+  float h, m;
 };
 
 constexpr float kU2 = 3.5527136788005009e-15f;   // 2^-48
@@ -233,13 +244,12 @@ constexpr float kK2 = 6.0f * kU2;
 // EA / EB: whether a / b carry an inherited error bound (accumulators do;
 // the coefficients of a node are exact and have no inherited term).
 template <bool EA, bool EB>
-__device__ __forceinline__ DF df_step(float ah, float al, float ea, float ta, const P3& X,
+__device__ __forceinline__ DF df_step(float ah, float al, float ea, float ta, const P2& X,
                                       float bh, float bl, float eb, float tb) {
   float p = ah * X.h;
   float pe = __builtin_fmaf(ah, X.h, -p);
   pe = __builtin_fmaf(ah, X.m, pe);
   pe = __builtin_fmaf(al, X.h, pe);
-  pe = __builtin_fmaf(ah, X.l, pe);
   float s = p + bh;
   float bb = s - p;
   float se = (p - (s - bb)) + (bh - bb);
@@ -258,7 +268,8 @@ __device__ __forceinline__ DF df_step(float ah, float al, float ea, float ta, co
 struct ArDF32 {
   using Op = OpF32;
   using Acc = DF;
-  using Pow = P3;
+  using Pow = P2;
+  using Full = P3;   // table entries at full precision, for products of entries
   using In = double;
   static __device__ __forceinline__ const Op* ops(const DevTree& t) { return t.ops32; }
   static __device__ __forceinline__ Acc fma_ca(const Op& o, const Pow& X, const Acc& top) {
@@ -279,32 +290,25 @@ struct ArDF32 {
     return df_step<true, false>(a.h, a.l, a.e, a.t, X, 0.f, 0.f, 0.f, 0.f);
   }
   static __device__ __forceinline__ Pow off_table(In xv, const Op& o) {
-    // binary exponentiation in double-double, split into three floats
+    // binary exponentiation in double-double, rounded to two floats
     DD r{1.0, 0.0}, b{xv, 0.0};
     for (uint32_t d = op_deg(o.deg); d; d >>= 1) {
       if (d & 1u) r = dd_mul(r, b);
       b = dd_mul(b, b);
     }
     const float h = (float)r.h;
-    const double dd = (r.h - (double)h) + r.l;
-    const float m = (float)dd;
-    return P3{h, m, (float)(dd - (double)m)};
+    return P2{h, (float)((r.h - (double)h) + r.l)};
   }
-  // the product of two table powers, in double-double, split again
-  static __device__ __forceinline__ Pow pair(const Pow& a, const Pow& b) {
+  // the product of two full-precision table powers, in double-double, split
+  // into three floats again
+  static __device__ __forceinline__ Full pair(const Full& a, const Full& b) {
     const DD r = dd_mul(DD{(double)a.h + (double)a.m, (double)a.l}, DD{(double)b.h + (double)b.m, (double)b.l});
     const float h = (float)r.h;
     const double d = (r.h - (double)h) + r.l;
     const float m = (float)d;
     return P3{h, m, (float)(d - (double)m)};
   }
-  static __device__ __forceinline__ P3 split3(double v) {
-    float h = (float)v;
-    double r = v - (double)h;
-    float m = (float)r;
-    float l = (float)(r - (double)m);
-    return P3{h, m, l};
-  }
+  static __device__ __forceinline__ Pow to_pow(const Full& f) { return P2{f.h, f.m}; }
 };
 
 // Interval walk.  A value is an interval [lo, hi] of FP64 numbers; the
@@ -370,6 +374,8 @@ struct ArIV {
   using Acc = IV;
   using Pow = IV;
   using In = IV;
+  using Full = Pow;
+  static __device__ __forceinline__ Pow to_pow(const Pow& f) { return f; }
   static __device__ __forceinline__ const Op* ops(const DevTree& t) { return t.ops64; }
   static __device__ __forceinline__ Acc fma_ca(const Op& o, const Pow& X, const Acc& top) {
     return iv_axb(u2d(o.a), X, top.lo, top.hi);
@@ -488,8 +494,8 @@ struct TabM61 {
   __device__ __forceinline__ uint64_t get(uint32_t i) const { return pm[i]; }
 };
 
-// Three-float powers for the double-float walk: the double-double value of
-// the chain split into h + m + l (72 bits).
+// Three-float powers for the double-float walk's table: the double-double
+// value of the chain split into h + m + l (72 bits); the walk reads h + m.
 __device__ __forceinline__ P3 split3_dd(DD r) {
   float h = (float)r.h;
   double d = (r.h - (double)h) + r.l;
@@ -501,7 +507,7 @@ __device__ __forceinline__ P3 split3_dd(DD r) {
 template <int CAP>
 struct TabP3 {
   P3 pm[CAP];             // entry i at pm[i] (private)
-  __device__ __forceinline__ void build(const DevTree& tr, const double* x, RegPow<P3>& rp) {
+  __device__ __forceinline__ void build(const DevTree& tr, const double* x, RegPow<P2>& rp) {
     // the chain runs on the three-float values (h + m is exact in FP64, so
     // each product is a double-double one)
     for (int c = 0; c < tr.n_chain; ++c) {
@@ -515,9 +521,10 @@ struct TabP3 {
       }
     }
 #pragma unroll
-    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? pm[k] : P3{0.f, 0.f, 0.f};
+    for (int k = 0; k < kRegPowers; ++k) rp.r[k] = k < tr.n_table ? get(k) : P2{0.f, 0.f};
   }
-  __device__ __forceinline__ P3 get(uint32_t i) const { return pm[i]; }
+  __device__ __forceinline__ P2 get(uint32_t i) const { return P2{pm[i].h, pm[i].m}; }
+  __device__ __forceinline__ P3 full(uint32_t i) const { return pm[i]; }
 };
 
 // Interval tables: the chain runs on bounds of |l|^d and |h|^d (l, h the ends
@@ -621,6 +628,7 @@ struct Walker {
   using Op = typename Ar::Op;
   using Acc = typename Ar::Acc;
   using Pow = typename Ar::Pow;
+  using Full = typename Ar::Full;
   using In = typename Ar::In;
   using Tab = typename TabFor<Ar, table_cap<PPL>()>::T;
 
@@ -672,9 +680,9 @@ struct Walker {
     } else {
       const uint32_t p1 = op_pidx(o.info), p2 = op_pidx2(o.info);
       if (p2 != kNoPair) {
-        const Pow a = Ar::pair(getany(j, p1), getany(j, p2));
-        if (op_deg(o.deg) & kThirdBit) return Ar::pair(a, getany(j, op_deg(o.deg) & 0xFFu));
-        return a;
+        const Full a = Ar::pair(full(j, p1), full(j, p2));
+        if (op_deg(o.deg) & kThirdBit) return Ar::to_pow(Ar::pair(a, full(j, op_deg(o.deg) & 0xFFu)));
+        return Ar::to_pow(a);
       }
       if constexpr (OFFT) return Ar::off_table(xvar(j, op_var(o.info)), o);
       return getany(j, p1);
@@ -686,6 +694,11 @@ struct Walker {
     if constexpr (lds_tier<Ar, DMAX>())
       if (i < (uint32_t)(kRegPowers + kLdsPowers)) return lt.get(i, j);
     return tab[j].get(i);
+  }
+  // entry i of point j's table at full precision (for products of entries)
+  __device__ __forceinline__ Full full(int j, uint32_t i) const {
+    if constexpr (std::is_same_v<Full, Pow>) return getany(j, i);
+    else return tab[j].full(i);
   }
   // entry i of point j's table, wherever it lives
   __device__ __forceinline__ Pow getany(int j, uint32_t i) const {
