@@ -130,6 +130,9 @@ def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, load: float):
         prepared.append((r.arrival_s, t, pts, out, m))
     torch.cuda.synchronize()
     budget = 2 << 30
+    # FP32 operations of the compensated walks of one pass over the stream
+    step_ops = float(sum(sum(k * o for k, o in zip(t.info.n_ops_kind, DF32_OPS_BY_KIND)) * m.points.shape[1]
+                         for _, t, _, _, m in prepared))
 
     srv = fpe.Server(hbm_budget=budget, max_inflight=64)
     t0 = time.perf_counter()
@@ -140,7 +143,7 @@ def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, load: float):
     st = srv.stats()
     sat = {"requests": nreq, "wall_s": wall_sat, "term_evals": st.term_evals,
            "term_evals_per_s": st.term_evals / wall_sat, "batches": st.batches,
-           "fallback_frac": st.fallback_frac}
+           "fallback_frac": st.fallback_frac, "df32_step_ops": step_ops}
     srv.close()
     sat_rps = nreq / wall_sat
 
@@ -273,6 +276,8 @@ def main():
     ap.add_argument("--cpu-points", type=int, default=600_000)
     ap.add_argument("--no-extra", action="store_true", help="skip the served, mod-p and composition phases")
     ap.add_argument("--served-requests", type=int, default=400)
+    ap.add_argument("--served-only", action="store_true",
+                    help="run only the served stream (for a profiler run of the fused kernels) and print its results")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="after the timed steps, copy a device buffer of this many bytes three times "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -288,6 +293,10 @@ def main():
     import paper_1307_5655_amd as fpe
 
     dev = torch.device("cuda:0")
+    if args.served_only:
+        served, latency = served_phase(fpe, fpe_inputs, torch, dev, args.served_requests, load=0.8)
+        print(json.dumps({"served": {"saturation": served, "poisson": latency}}), flush=True)
+        return
     degrees = (3000, 5000)
     schemes = ("balanced", "estrin", "horner")
     forms = (("f32c", fpe.F32C), ("f64", fpe.F64))

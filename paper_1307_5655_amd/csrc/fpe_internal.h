@@ -203,7 +203,7 @@ constexpr int kMaxTable = 48;   // power-table entries held per point (compositi
 constexpr int kTableCap = 16;   // smallest table size the compiler tries
 constexpr int kTableCapMulti = 32;   // largest table of the kernels with several points per lane
 constexpr int kMaxServe = 256;  // requests per fused launch
-constexpr int kServeGrid = 4096;   // fixed grid of the fused kernels (workgroups)
+constexpr int kServeGrid = 16384;  // fixed grid of the fused kernels (workgroups)
 // Fused served launch (walk.hip).
 struct ServeKernels {
   const void* zero;       // k_serve_zero(WorkTable*)

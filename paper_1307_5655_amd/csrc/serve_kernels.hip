@@ -44,8 +44,10 @@ __global__ __launch_bounds__(kBlock) void k_serve_walk(WorkTable* wt) {
     } else {
       // the walk without on-the-fly powers (no coordinates kept) when the
       // tree has none, which is the usual case
-      const DF rr = it.tree.n_offtable == 0 ? walk_point<ArDF32, DMAX, false>(it.tree, x, lds)
-                                            : walk_point<ArDF32, DMAX, true>(it.tree, x, lds);
+      DF rr;
+      if (it.tree.n_offtable != 0) rr = walk_point<ArDF32, DMAX, true>(it.tree, x, lds);
+      else if (DMAX > 2 && it.tree.depth <= 2) rr = walk_point<ArDF32, 2, false>(it.tree, x, lds);
+      else rr = walk_point<ArDF32, DMAX, false>(it.tree, x, lds);
       if (in) {
         double y;
         float cond;

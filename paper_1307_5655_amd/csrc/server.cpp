@@ -99,8 +99,8 @@ struct Slot {
   WorkTable* host[2] = {nullptr, nullptr};     // pinned staging
   WorkTable* dev[2] = {nullptr, nullptr};
   int64_t* host_counters[2] = {nullptr, nullptr};   // pinned copy-back
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t exec = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};   // one graph per table, launched only if it has work
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
   void* args[2][1];
   WorkTable* argv[2];
   hipEvent_t done_ev = nullptr;
@@ -154,14 +154,15 @@ fpe_status build_slot(fpe_server* s, Slot& sl) {
   }
   if (hipEventCreateWithFlags(&sl.done_ev, hipEventDisableTiming) != hipSuccess)
     return fail(FPE_EDEVICE, "server: event creation failed");
-  // graph: per table  copy -> zero -> walk -> fallback -> copy back
-  if (hipGraphCreate(&sl.graph, 0) != hipSuccess) return fail(FPE_EDEVICE, "server: hipGraphCreate failed");
+  // one graph per table: copy -> zero -> walk -> fallback -> copy back (a
+  // batch launches the graph of a table only when the table has requests)
   ServeKernels K = serve_kernels();
   for (int c = 0; c < 2; ++c) {
+    if (hipGraphCreate(&sl.graph[c], 0) != hipSuccess) return fail(FPE_EDEVICE, "server: hipGraphCreate failed");
     sl.argv[c] = sl.dev[c];
     sl.args[c][0] = &sl.argv[c];
     hipGraphNode_t cp, z, w, f, back;
-    if (hipGraphAddMemcpyNode1D(&cp, sl.graph, nullptr, 0, sl.dev[c], sl.host[c], tb, hipMemcpyHostToDevice) !=
+    if (hipGraphAddMemcpyNode1D(&cp, sl.graph[c], nullptr, 0, sl.dev[c], sl.host[c], tb, hipMemcpyHostToDevice) !=
         hipSuccess)
       return fail(FPE_EDEVICE, "server: graph memcpy node failed");
     hipKernelNodeParams zp{};
@@ -170,7 +171,7 @@ fpe_status build_slot(fpe_server* s, Slot& sl) {
     zp.blockDim = dim3(256);
     zp.sharedMemBytes = 0;
     zp.kernelParams = sl.args[c];
-    if (hipGraphAddKernelNode(&z, sl.graph, &cp, 1, &zp) != hipSuccess)
+    if (hipGraphAddKernelNode(&z, sl.graph[c], &cp, 1, &zp) != hipSuccess)
       return fail(FPE_EDEVICE, "server: graph kernel node failed");
     hipKernelNodeParams wp{};
     wp.func = (void*)(c == 0 ? K.walk8 : K.walk16);
@@ -178,20 +179,20 @@ fpe_status build_slot(fpe_server* s, Slot& sl) {
     wp.blockDim = dim3(64);
     wp.sharedMemBytes = (unsigned)K.walk_lds;
     wp.kernelParams = sl.args[c];
-    if (hipGraphAddKernelNode(&w, sl.graph, &z, 1, &wp) != hipSuccess)
+    if (hipGraphAddKernelNode(&w, sl.graph[c], &z, 1, &wp) != hipSuccess)
       return fail(FPE_EDEVICE, "server: graph kernel node failed");
     hipKernelNodeParams fp = wp;
     fp.func = (void*)(c == 0 ? K.fallback8 : K.fallback16);
     fp.sharedMemBytes = (unsigned)K.fallback_lds;
     fp.gridDim = dim3(kServeGrid);
-    if (hipGraphAddKernelNode(&f, sl.graph, &w, 1, &fp) != hipSuccess)
+    if (hipGraphAddKernelNode(&f, sl.graph[c], &w, 1, &fp) != hipSuccess)
       return fail(FPE_EDEVICE, "server: graph kernel node failed");
-    if (hipGraphAddMemcpyNode1D(&back, sl.graph, &f, 1, sl.host_counters[c], table_counters(sl.dev[c]),
+    if (hipGraphAddMemcpyNode1D(&back, sl.graph[c], &f, 1, sl.host_counters[c], table_counters(sl.dev[c]),
                                 sizeof(int64_t) * kMaxServe, hipMemcpyDeviceToHost) != hipSuccess)
       return fail(FPE_EDEVICE, "server: graph memcpy node failed");
+    if (hipGraphInstantiate(&sl.exec[c], sl.graph[c], nullptr, nullptr, 0) != hipSuccess)
+      return fail(FPE_EDEVICE, "server: hipGraphInstantiate failed");
   }
-  if (hipGraphInstantiate(&sl.exec, sl.graph, nullptr, nullptr, 0) != hipSuccess)
-    return fail(FPE_EDEVICE, "server: hipGraphInstantiate failed");
   (void)s;
   return FPE_OK;
 }
@@ -234,8 +235,10 @@ bool try_launch(fpe_server* s, Slot& sl) {
     sl.host[c]->total_blocks = blocks[c];
     table_prefix(sl.host[c])[n[c]] = blocks[c];
   }
-  if (hipGraphLaunch(sl.exec, s->stream) != hipSuccess || hipEventRecord(sl.done_ev, s->stream) != hipSuccess)
-    s->dev_err = "server: graph launch failed";
+  bool ok = true;
+  for (int c = 0; c < 2; ++c)
+    if (n[c] > 0) ok = ok && hipGraphLaunch(sl.exec[c], s->stream) == hipSuccess;
+  if (!ok || hipEventRecord(sl.done_ev, s->stream) != hipSuccess) s->dev_err = "server: graph launch failed";
   sl.busy = true;
   s->batches++;
   sl.busy_start = std::chrono::duration<double>(Clock::now() - s->t0).count();
@@ -443,8 +446,10 @@ void fpe_server_destroy(fpe_server* s) {
   }
   (void)hipStreamSynchronize(s->stream);
   for (auto& sl : s->slots) {
-    if (sl.exec) (void)hipGraphExecDestroy(sl.exec);
-    if (sl.graph) (void)hipGraphDestroy(sl.graph);
+    for (int c = 0; c < 2; ++c) {
+      if (sl.exec[c]) (void)hipGraphExecDestroy(sl.exec[c]);
+      if (sl.graph[c]) (void)hipGraphDestroy(sl.graph[c]);
+    }
     if (sl.done_ev) (void)hipEventDestroy(sl.done_ev);
     for (int c = 0; c < 2; ++c) {
       if (sl.host[c]) (void)hipHostFree(sl.host[c]);
