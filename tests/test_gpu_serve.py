@@ -121,3 +121,46 @@ def test_serve_requests_arriving_during_a_batch(dev):
     for (t, dom, pts, m), o in zip(reqs, outs):
         assert np.array_equal(o.cpu().numpy(), fpe.evaluate(t, pts).cpu().numpy())
     srv.close()
+
+
+def test_serve_tables_by_condition_output_and_table_size(dev):
+    """Requests with and without condition numbers, FP64 requests and
+    compensated trees whose powers do not fit the multi-point walks (the
+    direct scheme: large tables, powers on the fly) are batched into separate
+    work tables; every value and condition number matches the request alone."""
+    say("serve: condition output, FP64, large tables")
+    g = np.random.default_rng([13075655, 500, 9])
+    reqs = []
+    for k in range(24):
+        v = 1 + k % 3
+        m = fpe_inputs.random_multi_f64(v, int(g.integers(20, 600)), int(g.integers(1000, 20_000)), g)
+        scheme = ["horner", "estrin", "balanced", "direct"][k % 4]
+        dom = fpe.F64 if k % 6 == 5 else fpe.F32C
+        want_cond = dom == fpe.F32C and k % 2 == 0
+        reqs.append((scheme, dom, want_cond, m))
+    prepared = []
+    for scheme, dom, want_cond, m in reqs:
+        t = fpe.Tree(m.exps, m.coeffs, scheme, dom).upload(dev)
+        pts = [torch.from_numpy(np.ascontiguousarray(m.points[j])).to(dev) for j in range(m.points.shape[0])]
+        prepared.append((t, dom, want_cond, pts, m))
+    assert any(t.info.n_table > 32 or t.info.n_offtable > 0 for t, *_ in prepared)
+    alone = []
+    for t, dom, want_cond, pts, m in prepared:
+        c = torch.empty(pts[0].numel(), dtype=torch.float32, device=dev) if want_cond else None
+        y = fpe.evaluate(t, pts, cond_out=c)
+        alone.append((y.cpu().numpy(), None if c is None else c.cpu().numpy()))
+    srv = fpe.Server(hbm_budget=64 << 20, max_inflight=32)
+    outs = []
+    for t, dom, want_cond, pts, m in prepared:
+        o = torch.full((pts[0].numel(),), np.nan, dtype=torch.float64, device=dev)
+        c = torch.full((pts[0].numel(),), np.nan, dtype=torch.float32, device=dev) if want_cond else None
+        outs.append((o, c))
+        srv.submit(t, pts, o, domain=dom, cond_out=c)
+    srv.drain()
+    for k, ((o, c), (ya, ca)) in enumerate(zip(outs, alone)):
+        assert np.array_equal(o.cpu().numpy(), ya), k
+        if c is not None:
+            assert np.array_equal(c.cpu().numpy(), ca), k
+    st = srv.stats()
+    assert st.completed == st.submitted == len(prepared)
+    srv.close()
