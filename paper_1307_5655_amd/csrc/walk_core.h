@@ -561,8 +561,8 @@ struct TabIV {
 // next most used after the register copies) of every point of a wavefront,
 // stored as 32-bit planes [entry][word][point j][lane] so a wavefront reads 64
 // consecutive words (no bank conflicts).  One wavefront per workgroup, so a
-// workgroup's dynamic LDS is walk_lds_bytes<Ar, PPL>(): 6 KB for the
-// double-float walk at two points per lane.  Entries beyond the tier stay in
+// workgroup's dynamic LDS is walk_lds_bytes<Ar, PPL>(): 4 KB for the
+// double-float walk (two-float powers) at two points per lane.  Entries beyond the tier stay in
 // private memory; the tier keeps the table's hot part out of it, whose
 // working set is far beyond the caches at full occupancy.
 template <class E, int PPL>
