@@ -203,10 +203,12 @@ bool try_launch(fpe_server* s, Slot& sl) {
   sl.tickets[1].clear();
   int n[2] = {0, 0};
   int64_t blocks[2] = {0, 0};
+  // admit in arrival order (first come, first admitted) ...
+  std::vector<Req*> adm[2];
   while (!s->queue.empty() && s->inflight < s->max_inflight) {
     Req& q = s->reqs[s->queue.front()];
     const int c = q.r.tree->depth <= 8 ? 0 : 1;
-    if (n[c] == kMaxServe) break;
+    if ((int)adm[c].size() == kMaxServe) break;
     size_t need = req_ws_bytes(q.r);
     size_t off = 0;
     if (!s->pool.alloc(need, off)) break;     // wait for memory to free up (FIFO)
@@ -214,20 +216,32 @@ bool try_launch(fpe_server* s, Slot& sl) {
     q.ws_bytes = need;
     s->queue.pop_front();
     s->inflight++;
-    WorkItem& it = table_items(sl.host[c])[n[c]];
-    std::memset(&it, 0, sizeof it);
-    it.tree = dev_view(q.r.tree);
-    for (int j = 0; j < q.r.tree->nvars; ++j) it.pts[j] = q.r.pts[j];
-    it.out = q.r.out;
-    it.cond = q.r.cond_out;
-    it.list = (int32_t*)(s->pool_dev + off);
-    it.npts = q.r.npts;
-    it.tol = q.r.tol > 0 ? q.r.tol : 1e-12;
-    it.domain = q.r.domain;
-    table_prefix(sl.host[c])[n[c]] = blocks[c];
-    blocks[c] += (q.r.npts + 63) / 64;
-    sl.tickets[c].push_back(q.ticket);
-    n[c]++;
+    adm[c].push_back(&q);
+  }
+  // ... and lay the batch out with the longest walks first: the fused grid
+  // takes blocks in table order, so the blocks that run longest start first
+  // and the batch does not end on a tail of them
+  for (int c = 0; c < 2; ++c)
+    std::stable_sort(adm[c].begin(), adm[c].end(),
+                     [](const Req* x, const Req* y) { return x->r.tree->ops64.size() > y->r.tree->ops64.size(); });
+  for (int c = 0; c < 2; ++c) {
+    for (Req* qp : adm[c]) {
+      Req& q = *qp;
+      WorkItem& it = table_items(sl.host[c])[n[c]];
+      std::memset(&it, 0, sizeof it);
+      it.tree = dev_view(q.r.tree);
+      for (int j = 0; j < q.r.tree->nvars; ++j) it.pts[j] = q.r.pts[j];
+      it.out = q.r.out;
+      it.cond = q.r.cond_out;
+      it.list = (int32_t*)(s->pool_dev + q.ws_off);
+      it.npts = q.r.npts;
+      it.tol = q.r.tol > 0 ? q.r.tol : 1e-12;
+      it.domain = q.r.domain;
+      table_prefix(sl.host[c])[n[c]] = blocks[c];
+      blocks[c] += (q.r.npts + 63) / 64;
+      sl.tickets[c].push_back(q.ticket);
+      n[c]++;
+    }
   }
   if (n[0] + n[1] == 0) return false;
   for (int c = 0; c < 2; ++c) {
