@@ -90,7 +90,12 @@ __global__ __launch_bounds__(kBlock) void k_serve_fallback(WorkTable* wt) {
     double x[8];
 #pragma unroll
     for (int j = 0; j < 8; ++j) x[j] = (i >= 0 && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
-    const DD rr = walk_point<ArDD, DMAX, true>(it.tree, x, lds);
+    // as in the walk: no coordinates kept when every power is in the table,
+    // and the chain-like walk for trees of depth <= 2
+    DD rr;
+    if (it.tree.n_offtable != 0) rr = walk_point<ArDD, DMAX, true>(it.tree, x, lds);
+    else if (DMAX > 2 && it.tree.depth <= 2) rr = walk_point<ArDD, 2, false>(it.tree, x, lds);
+    else rr = walk_point<ArDD, DMAX, false>(it.tree, x, lds);
     if (i >= 0) it.out[i] = rr.h + rr.l;
   }
 }
