@@ -158,3 +158,21 @@ def test_interval_edge_cases(dev):
     raw = torch.zeros(2 * 8 + 1, dtype=torch.float64, device=dev)
     with pytest.raises(fpe.FpeError):
         fpe.evaluate(t, [raw[1:].view(8, 2)])
+
+
+def test_interval_subnormal_and_huge_magnitudes(dev):
+    """Bounds that land in the subnormal range or near the top of the FP64
+    range still enclose the exact interval value."""
+    say("interval subnormal / huge magnitudes")
+    cases = [
+        ([[0], [1], [2]], [1e-300, 1e-160, 3e-150], [(1e-160, 1e-160), (-2e-160, 1e-161), (-1e-155, -1e-156)]),
+        ([[0], [1], [3]], [1.0, -1e150, 1e100], [(1e50, 1e50), (-1e50, 2e50), (-3e50, -1e50)]),
+    ]
+    for ex, co, boxes in cases:
+        ex = np.array(ex, dtype=np.int32)
+        co = np.array(co)
+        terms = [((int(e[0]),), float(c)) for e, c in zip(ex, co)]
+        for scheme in ("horner", "estrin"):
+            b = np.array(boxes, dtype=np.float64)[None]
+            got, t = gpu_boxes(ex, co, scheme, b, dev)
+            check_against_oracle(got, t, terms, scheme, b, range(b.shape[1]))

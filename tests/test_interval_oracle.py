@@ -85,3 +85,34 @@ def test_inclusion_property(name):
         lo, hi = interval.tree_interval(nodes, [(Fraction(a), Fraction(b))])
         for t in np.linspace(a, b, 9):
             assert lo <= exact.exact_value(terms, [float(t)]) <= hi
+
+
+def test_outward_rounding_rule_encloses_round_to_nearest():
+    """The interval walk moves each round-to-nearest result r outward by
+    RN(RN(r -/+ |r| 2^-52) -/+ 2^-1074).  For exact values z (random, and at
+    binade edges, in the subnormal range and near overflow), with r = RN(z)
+    computed exactly: dn(r) <= z <= up(r)."""
+    F = Fraction
+    tiny = F(2) ** -1074
+
+    def rn(q):                     # correctly rounded (float() of a Fraction)
+        return float(q)
+
+    def dn(r):
+        return rn(F(rn(F(r) - abs(F(r)) * F(2) ** -52)) - tiny)
+
+    def up(r):
+        return rn(F(rn(F(r) + abs(F(r)) * F(2) ** -52)) + tiny)
+
+    g = np.random.default_rng(21)
+    zs = []
+    for e in (-1074, -1060, -1022, -1000, -52, -1, 0, 1, 52, 500, 1020):
+        for _ in range(20):
+            m = F(int(g.integers(1, 2 ** 62)), 2 ** 62)        # (0, 1)
+            zs.append(m * F(2) ** e)
+        zs.append(F(2) ** e)                                   # binade edges
+        zs.append(F(2) ** e * (1 - F(1, 2 ** 60)))
+    zs += [-z for z in zs] + [F(0)]
+    for z in zs:
+        r = rn(z)
+        assert F(dn(r)) <= z <= F(up(r)), z
