@@ -143,6 +143,9 @@ typedef struct {
   int32_t n_pair_ops;      /* walk steps whose power is the product of two table entries */
   int32_t n_ops_kind[5];   /* walk steps by kind: LEAF_ADD (a X + top), NODE_OPEN (top X + b),
                               LEAF_OPEN (push a X + b), NODE_ADD (below += top X; pop), END */
+  int32_t domain;          /* fpe_domain the tree was compiled for */
+  uint64_t modulus;        /* FPE_MODP: the modulus, else 0 */
+  int64_t batch;           /* instances (composition), else 1 */
 } fpe_tree_info;
 
 fpe_status fpe_tree_get_info(const fpe_tree* t, fpe_tree_info* info);

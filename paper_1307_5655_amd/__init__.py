@@ -49,7 +49,8 @@ class TreeInfo(ctypes.Structure):
                 ("walk_depth", ctypes.c_int32), ("n_powers", ctypes.c_int32),
                 ("n_table", ctypes.c_int32), ("n_chain", ctypes.c_int32),
                 ("n_offtable", ctypes.c_int32), ("n_pair_ops", ctypes.c_int32),
-                ("n_ops_kind", ctypes.c_int32 * 5)]
+                ("n_ops_kind", ctypes.c_int32 * 5), ("domain", ctypes.c_int32),
+                ("modulus", ctypes.c_uint64), ("batch", ctypes.c_int64)]
 
 
 class EvalOpts(ctypes.Structure):
@@ -179,13 +180,13 @@ class Tree:
         self.info = info
 
     @classmethod
-    def _from_handle(cls, h, domain, modulus, batch):
+    def _from_handle(cls, h):
         self = cls.__new__(cls)
         self._h = h
         info = TreeInfo()
         _check(lib.fpe_tree_get_info(h, ctypes.byref(info)))
         self.info = info
-        self.nvars, self.domain, self.modulus, self.batch = info.nvars, domain, modulus, batch
+        self.nvars, self.domain, self.modulus, self.batch = info.nvars, info.domain, info.modulus, info.batch
         self._dev = None
         return self
 
@@ -240,10 +241,11 @@ class Tree:
         return buf.raw[: n.value]
 
     @classmethod
-    def deserialize(cls, data: bytes, domain=F64, modulus=0, batch=1):
+    def deserialize(cls, data: bytes):
+        """A tree from ``serialize()``; its domain, modulus and batch come from the data."""
         h = ctypes.c_void_p()
         _check(lib.fpe_tree_deserialize(data, len(data), ctypes.byref(h)))
-        return cls._from_handle(h, domain, modulus, batch)
+        return cls._from_handle(h)
 
 
 def workspace_bytes(tree: Tree, npts: int) -> int:
@@ -261,11 +263,20 @@ def evaluate(tree: Tree, pts, out=None, tol: float = 1e-12, force: int = 0, cond
     if tree._dev is None:
         raise FpeError(-1, "tree is not uploaded")
     pts = list(pts) if isinstance(pts, (list, tuple)) else [pts]
+    if len(pts) != tree.nvars:
+        raise FpeError(-1, f"{tree.nvars} point arrays expected, {len(pts)} given")
     npts = pts[0].shape[0] if tree.domain == IVAL else pts[0].numel()
+    # the library takes raw pointers: check the sizes it will read and write
+    shape = (npts, 2) if tree.domain == IVAL else (npts,)
+    for p in pts:
+        if tuple(p.shape) != shape or not p.is_contiguous() or p.element_size() != 8:
+            raise FpeError(-1, f"point arrays must be contiguous 8-byte tensors of shape {shape}")
     if out is None:
         dt = torch.int64 if tree.domain == MODP else torch.float64
-        shape = (npts, 2) if tree.domain == IVAL else (npts,)
         out = torch.empty(shape, dtype=dt, device=pts[0].device)
+    elif out.numel() < (2 * npts if tree.domain == IVAL else npts) or not out.is_contiguous() \
+            or out.element_size() != 8:
+        raise FpeError(-1, "output must be a contiguous 8-byte tensor with a value (or interval) per point")
     arr = (ctypes.c_void_p * 8)(*[p.data_ptr() for p in pts])
     opts = EvalOpts(tol, force, points_per_lane, cond_out.data_ptr() if cond_out is not None else None,
                     flags_out.data_ptr() if flags_out is not None else None, None, 0,
@@ -316,6 +327,10 @@ class Server:
         self._h = h
 
     def submit(self, tree: Tree, pts, out, domain=F32C, tol=1e-12, cond_out=None) -> int:
+        n = pts[0].numel()
+        if len(pts) != tree.nvars or any(p.numel() != n or not p.is_contiguous() for p in pts) \
+                or out.numel() < n or (cond_out is not None and cond_out.numel() < n):
+            raise FpeError(-1, "one contiguous point array per variable, all of one length, and outputs that long")
         r = Request()
         r.tree = tree.handle
         for j, p in enumerate(pts):

@@ -98,6 +98,9 @@ fpe_status fpe_tree_get_info(const fpe_tree* t, fpe_tree_info* info) {
   info->n_offtable = t->n_offtable;
   info->n_pair_ops = t->n_pairs;
   for (int k = 0; k < 5; ++k) info->n_ops_kind[k] = t->n_kind[k];
+  info->domain = t->domain;
+  info->modulus = t->modulus;
+  info->batch = t->batch;
   return FPE_OK;
 }
 

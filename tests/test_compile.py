@@ -172,7 +172,8 @@ def test_serialize_roundtrip():
     co = rng.uniform(-1, 1, len(ex))
     t = fpe.Tree(ex, co, "balanced", fpe.F32C)
     blob = t.serialize()
-    t2 = fpe.Tree.deserialize(blob, fpe.F32C)
+    t2 = fpe.Tree.deserialize(blob)
+    assert t2.domain == fpe.F32C and t2.batch == 1
     assert t2.serialize() == blob
     assert np.array_equal(t2.nodes(), t.nodes())
     with pytest.raises(fpe.FpeError):
@@ -226,3 +227,12 @@ def test_interval_trees_share_the_shape_and_take_no_power_products(scheme):
     assert tiv.info.n_table <= 48
     back = fpe.Tree.deserialize(tiv.serialize())
     assert np.array_equal(back.nodes(), tiv.nodes())
+    assert back.domain == fpe.IVAL
+
+
+def test_tree_info_reports_domain_modulus_and_batch():
+    e = np.array([[0], [3], [5]], dtype=np.int32)
+    t = fpe.Tree(e, np.array([[1, 2, 3], [4, 5, 6]], dtype=np.uint64), "estrin", fpe.MODP, fpe.P31)
+    assert (t.info.domain, t.info.modulus, t.info.batch) == (fpe.MODP, fpe.P31, 2)
+    back = fpe.Tree.deserialize(t.serialize())
+    assert (back.domain, back.modulus, back.batch) == (fpe.MODP, fpe.P31, 2)
