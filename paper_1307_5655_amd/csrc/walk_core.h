@@ -48,16 +48,19 @@ __device__ __forceinline__ DD dd_mul(DD a, DD b) {
   return {s, e - (s - p)};
 }
 
+// a * x + b in double-double; AL / BL: whether a / b have a low word (a
+// coefficient is a plain double, so its terms are left out).
+template <bool AL = true, bool BL = true>
 __device__ __forceinline__ DD dd_fma(DD a, DD x, DD b) {
-  // a * x + b
   double p = a.h * x.h;
   double pe = __builtin_fma(a.h, x.h, -p);
   pe = __builtin_fma(a.h, x.l, pe);
-  pe = __builtin_fma(a.l, x.h, pe);
+  if constexpr (AL) pe = __builtin_fma(a.l, x.h, pe);
   double s = p + b.h;
   double bb = s - p;
   double se = (p - (s - bb)) + (b.h - bb);
-  se = se + (pe + b.l);
+  if constexpr (BL) se = se + (pe + b.l);
+  else se = se + pe;
   double h = s + se;
   return {h, se - (h - s)};
 }
@@ -151,13 +154,13 @@ struct ArDD {   // double-double walk (fallback), double-double powers
   static __device__ __forceinline__ Pow to_pow(const Pow& f) { return f; }
   static __device__ __forceinline__ const Op* ops(const DevTree& t) { return t.ops64; }
   static __device__ __forceinline__ Acc fma_ca(const Op& o, const Pow& X, const Acc& top) {
-    return dd_fma(DD{u2d(o.a), 0.0}, X, top);
+    return dd_fma<false, true>(DD{u2d(o.a), 0.0}, X, top);
   }
   static __device__ __forceinline__ Acc fma_tb(const Acc& top, const Pow& X, const Op& o) {
-    return dd_fma(top, X, DD{u2d(o.b), 0.0});
+    return dd_fma<true, false>(top, X, DD{u2d(o.b), 0.0});
   }
   static __device__ __forceinline__ Acc fma_ab(const Op& o, const Pow& X) {
-    return dd_fma(DD{u2d(o.a), 0.0}, X, DD{u2d(o.b), 0.0});
+    return dd_fma<false, false>(DD{u2d(o.a), 0.0}, X, DD{u2d(o.b), 0.0});
   }
   static __device__ __forceinline__ Acc fma_tt(const Acc& top, const Pow& X, const Acc& below) {
     return dd_fma(top, X, below);
