@@ -3,9 +3,14 @@
 
 namespace fpe {
 
+// The depth-6 walk with the LDS tier needs one VGPR more than five waves
+// per SIMD allow; asking for five keeps that occupancy.
+template <int DMAX, int PPL>
+constexpr int f64_waves_per_eu() { return DMAX == 6 && PPL == 4 ? 5 : 1; }
+
 template <int DMAX, int PPL, bool OFFT>
-__global__ __launch_bounds__(kBlock) void k_eval_f64(DevTree tr, Pts<double> P, int64_t npts,
-                                                     double* __restrict__ out) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(f64_waves_per_eu<DMAX, PPL>())))
+void k_eval_f64(DevTree tr, Pts<double> P, int64_t npts, double* __restrict__ out) {
   extern __shared__ __align__(16) char lds[];
   const int64_t base = (int64_t)blockIdx.x * kBlock * PPL + threadIdx.x;
   double x[PPL][8];

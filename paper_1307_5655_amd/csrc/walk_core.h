@@ -593,11 +593,11 @@ struct LdsTier {
   }
 };
 // Whether a kernel uses the tier: not for chain-like walks (depth <= 2, whose
-// few powers all sit in registers), and not for the FP64 depth-6 kernel, whose
-// occupancy the tier's addressing would lower by one wave (measured slower).
+// few powers all sit in registers).  (The FP64 depth-6 kernel asks for five
+// waves per SIMD, which the tier's addressing would otherwise lower by one.)
 template <class Ar, int DMAX>
 constexpr bool lds_tier() {
-  return DMAX > 2 && !(std::is_same_v<Ar, ArF64> && DMAX == 6);
+  return DMAX > 2;
 }
 template <class Ar, int DMAX, int PPL>
 constexpr size_t walk_lds_bytes() {
