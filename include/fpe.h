@@ -127,8 +127,9 @@ void fpe_tree_free(fpe_tree* t);
 /* Read-only view of the node array (valid while the tree lives). */
 fpe_status fpe_tree_nodes(const fpe_tree* t, const fpe_node** nodes, int64_t* n, int32_t* max_slot);
 
-/* Walk statistics: stack depth of the walk, size of the per-point power table,
- * length of the power chain, number of distinct partial degrees. */
+/* Walk statistics (stack depth of the walk, size of the per-point power table,
+ * length of the power chain, number of distinct partial degrees, steps by
+ * kind) and what the tree was compiled for (domain, modulus, batch). */
 typedef struct {
   int64_t n_nodes;
   int64_t n_terms;         /* nonzero input terms (n_nodes minus junctions) */
