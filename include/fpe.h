@@ -57,8 +57,10 @@ typedef enum {
   FPE_F64 = 0,   /* plain FP64 walk, one fused multiply-add per node (Section 2.1) */
   FPE_F32C = 1,  /* compensated FP32 (double-float) walk + FP64 fallback */
   FPE_MODP = 2,  /* exact walk in Z/pZ, p = 2^61 - 1 for evaluation, 2^31 - 1 for composition */
-  FPE_IVAL = 3   /* interval walk (the abstract's interval coefficient type): FP64 bounds
+  FPE_IVAL = 3,  /* interval walk (the abstract's interval coefficient type): FP64 bounds
                     rounded outward, enclosing the tree's interval evaluation over a box */
+  FPE_BIGINT = 4 /* exact evaluation over the natural numbers at big-integer points
+                    (the workload of the Benchmarks section, Figure 1): fpe_eval_bigint */
 } fpe_domain;
 
 /* Function schemes (Section 1.1 and 1.2).  The argument of f is the degree n
@@ -111,7 +113,8 @@ typedef struct fpe_tree fpe_tree;
  *   nterms  >= 1 terms; exponents >= 0 and < 2^20; no monomial twice.
  *           Terms with a zero coefficient are dropped (all zero: FPE_EINVAL).
  *   coeffs  host array: double[nterms] for FPE_F64 / FPE_F32C / FPE_IVAL (finite;
- *           FPE_IVAL takes them as exact point coefficients), or
+ *           FPE_IVAL takes them as exact point coefficients), uint64_t[nterms]
+ *           for FPE_BIGINT (univariate; any value), or
  *           uint64_t[batch * nterms] residues < modulus for FPE_MODP (row r
  *           holds instance r; all rows share the exponents; the tree shape is
  *           taken from the union of nonzero positions).
@@ -207,6 +210,25 @@ fpe_status fpe_evaluate(const fpe_tree* t, const void* const* pts, int64_t npts,
  *   out  device uint32[batch * (deg_p * dq + 1)], coefficients by exponent
  *   workspace  device buffer of fpe_compose_workspace_bytes() bytes */
 size_t fpe_compose_workspace_bytes(const fpe_tree* t, int32_t dq);
+
+/* Exact evaluation over the natural numbers at big-integer points (the
+ * workload of the paper's Benchmarks section, Figure 1): for every point r of
+ * the batch, out[r] = p(x_r), with the tree (univariate, FPE_BIGINT, uint64
+ * coefficients) walked with big-integer values.
+ *   x    device uint32[batch * lx]: point r's limbs at r*lx, 16 bits per word
+ *        (values < 2^16), least significant first
+ *   out  device uint32[batch * lout]: p(x_r)'s 16-bit limbs, least significant
+ *        first, zero-padded; lout >= fpe_bigint_out_limbs(t, lx) (which is 0 if
+ *        more than 2^16 limbs would be needed: unsupported)
+ *   workspace  device buffer of fpe_bigint_workspace_bytes(t, lout, batch)
+ *        bytes, 256-byte aligned
+ * One wavefront walks one point; products are schoolbook over 16-bit limbs.
+ * Errors: FPE_EINVAL (not a FPE_BIGINT tree, lout too small, NULL), FPE_ENOMEM
+ * (workspace), FPE_EUNSUPPORTED (powers outside the table, lout > 2^16). */
+int32_t fpe_bigint_out_limbs(const fpe_tree* t, int32_t lx);
+size_t fpe_bigint_workspace_bytes(const fpe_tree* t, int32_t lout, int64_t batch);
+fpe_status fpe_eval_bigint(const fpe_tree* t, const uint32_t* x, int32_t lx, int64_t batch, uint32_t* out,
+                           int32_t lout, void* workspace, size_t workspace_bytes, void* stream);
 fpe_status fpe_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out,
                        void* workspace, size_t workspace_bytes, void* stream);
 

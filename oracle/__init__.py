@@ -17,6 +17,8 @@ Contents (each function cites the passage of the paper it follows):
 * ``compose``  exact composition p(q(x)) over Z/pZ by schoolbook expansion.
 * ``interval`` the tree's value over a box with exact interval operations
                (the interval coefficient type of the Abstract).
+* ``bigint``   p(x) over the natural numbers at big-integer points (the
+               Benchmarks section's workload), with 16-bit limb conversion.
 * ``native``   the same definitions in plain C for full-size samples and for
                the timed CPU baseline (built by ``oracle/build_native.sh``).
 

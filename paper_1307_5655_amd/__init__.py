@@ -16,7 +16,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libfpe.so")
 
-F64, F32C, MODP, IVAL = 0, 1, 2, 3
+F64, F32C, MODP, IVAL, BIGINT = 0, 1, 2, 3, 4
 DIRECT, HORNER, ESTRIN, BALANCED, BALANCED_FLOOR, THRESHOLD, TABLE = range(7)
 SCHEMES = {"direct": DIRECT, "horner": HORNER, "estrin": ESTRIN, "balanced": BALANCED,
            "balanced_floor": BALANCED_FLOOR, "threshold": THRESHOLD, "table": TABLE}
@@ -110,6 +110,9 @@ def _load():
         "fpe_server_drain": ([P], i32),
         "fpe_server_stats": ([P, ctypes.POINTER(Stats)], i32),
         "fpe_server_destroy": ([P], None),
+        "fpe_bigint_out_limbs": ([P, i32], i32),
+        "fpe_bigint_workspace_bytes": ([P, i32, i64], sz),
+        "fpe_eval_bigint": ([P, P, i32, i64, P, i32, P, sz, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -125,7 +128,7 @@ EXPORTED = ["fpe_last_error", "fpe_version", "fpe_compile", "fpe_tree_free", "fp
             "fpe_tree_serialize", "fpe_tree_deserialize", "fpe_workspace_bytes", "fpe_evaluate",
             "fpe_compose_workspace_bytes", "fpe_compose", "fpe_server_create", "fpe_server_submit",
             "fpe_server_poll", "fpe_server_wait", "fpe_server_drain", "fpe_server_stats",
-            "fpe_server_destroy"]
+            "fpe_server_destroy", "fpe_bigint_out_limbs", "fpe_bigint_workspace_bytes", "fpe_eval_bigint"]
 
 
 def _check(st: int):
@@ -160,7 +163,7 @@ class Tree:
         if exps.ndim == 1:
             exps = exps.reshape(-1, 1)
         nterms, nvars = exps.shape
-        if domain == MODP:
+        if domain in (MODP, BIGINT):
             c = np.ascontiguousarray(np.asarray(coeffs, dtype=np.uint64))
             batch = 1 if c.ndim == 1 else c.shape[0]
             c = c.reshape(batch, nterms)
@@ -294,6 +297,32 @@ def evaluate(tree: Tree, pts, out=None, tol: float = 1e-12, force: int = 0, cond
         opts.workspace_bytes = workspace.numel() - off
     _check(lib.fpe_evaluate(tree.handle, arr, npts, ctypes.c_void_p(out.data_ptr()),
                             ctypes.byref(opts), _stream_ptr(stream)))
+    return out
+
+
+def eval_bigint(tree: Tree, x, lout=None, out=None, workspace=None, stream=None):
+    """p(x_r) over the natural numbers for every point r: ``x`` is a device
+    int32 tensor [batch, lx] of 16-bit limbs (least significant first); the
+    result is [batch, lout] int32 limbs (values < 2^16)."""
+    import torch
+    if tree._dev is None:
+        raise FpeError(-1, "tree is not uploaded")
+    if x.dim() != 2 or not x.is_contiguous() or x.element_size() != 4:
+        raise FpeError(-1, "x must be a contiguous 32-bit tensor [batch, lx]")
+    batch, lx = x.shape
+    if lout is None:
+        lout = int(lib.fpe_bigint_out_limbs(tree.handle, lx))
+    if out is None:
+        out = torch.empty((batch, lout), dtype=torch.int32, device=x.device)
+    elif tuple(out.shape) != (batch, lout) or not out.is_contiguous() or out.element_size() != 4:
+        raise FpeError(-1, "out must be a contiguous 32-bit tensor [batch, lout]")
+    need = int(lib.fpe_bigint_workspace_bytes(tree.handle, lout, batch))
+    if workspace is None:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=x.device)
+    off = (-workspace.data_ptr()) % 256
+    _check(lib.fpe_eval_bigint(tree.handle, ctypes.c_void_p(x.data_ptr()), lx, batch,
+                               ctypes.c_void_p(out.data_ptr()), lout, ctypes.c_void_p(workspace.data_ptr() + off),
+                               workspace.numel() - off, _stream_ptr(stream)))
     return out
 
 

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfpe.so")
-SOURCES = ["compile.cpp", "api.cpp", "walk.hip", "eval_f64.hip", "eval_m61.hip", "eval_df32.hip", "eval_iv.hip",
+SOURCES = ["compile.cpp", "api.cpp", "walk.hip", "eval_f64.hip", "eval_m61.hip", "eval_df32.hip", "eval_iv.hip", "bigint.hip",
            "serve_kernels.hip", "compose.hip", "server.cpp"]
 EXTRA_SOURCES = []
 

@@ -155,6 +155,7 @@ fpe_status fpe_evaluate(const fpe_tree* t, const void* const* pts, int64_t npts,
   if (!t->dev) return fail(FPE_EINVAL, "tree is not uploaded");
   if (npts < 0) return fail(FPE_EINVAL, "npts < 0");
   if (t->batch != 1) return fail(FPE_EINVAL, "a batch tree is for fpe_compose");
+  if (t->domain == FPE_BIGINT) return fail(FPE_EINVAL, "a big-integer tree is evaluated by fpe_eval_bigint");
   if (npts == 0) return FPE_OK;
   if (!pts || !out) return fail(FPE_EINVAL, "NULL points or output");
   for (int j = 0; j < t->nvars; ++j)
@@ -284,6 +285,38 @@ fpe_status fpe_tree_deserialize(const void* buf, size_t bytes, fpe_tree** out) {
 }
 
 size_t fpe_compose_workspace_bytes(const fpe_tree* t, int32_t dq) { return compose_workspace_bytes(t, dq); }
+
+// Limbs that p(x) needs at most for points of lx limbs: deg * lx for x^deg,
+// four for the coefficient, and enough for the sum of the terms.
+static int64_t bigint_limbs_needed(const fpe_tree* t, int32_t lx) {
+  int64_t dp = 0;
+  for (size_t i = 0; i < t->nodes.size(); ++i) dp = std::max<int64_t>(dp, t->exps[i]);
+  int64_t extra = 1;
+  for (int64_t n = t->n_terms; n > 1; n >>= 16) ++extra;
+  return dp * lx + 4 + extra;
+}
+
+int32_t fpe_bigint_out_limbs(const fpe_tree* t, int32_t lx) {
+  if (!t || t->domain != FPE_BIGINT || lx < 1) return 0;
+  const int64_t n = bigint_limbs_needed(t, lx);
+  return n > kBigMaxLimbs ? 0 : (int32_t)n;
+}
+
+size_t fpe_bigint_workspace_bytes(const fpe_tree* t, int32_t lout, int64_t batch) {
+  if (!t || t->domain != FPE_BIGINT) return 0;
+  return bigint_workspace_bytes(t, lout, batch);
+}
+
+fpe_status fpe_eval_bigint(const fpe_tree* t, const uint32_t* x, int32_t lx, int64_t batch, uint32_t* out,
+                           int32_t lout, void* workspace, size_t workspace_bytes, void* stream) {
+  if (!t || !x || !out) return fail(FPE_EINVAL, "NULL argument");
+  if (!t->dev) return fail(FPE_EINVAL, "tree is not uploaded");
+  if (t->domain != FPE_BIGINT) return fail(FPE_EINVAL, "the tree is not compiled for FPE_BIGINT");
+  if (lx < 1) return fail(FPE_EINVAL, "points need at least one limb");
+  if (lout > kBigMaxLimbs) return fail(FPE_EUNSUPPORTED, "more output limbs than the kernel's columns hold");
+  if (lout < bigint_limbs_needed(t, lx)) return fail(FPE_EINVAL, "lout smaller than fpe_bigint_out_limbs()");
+  return launch_bigint(t, x, lx, batch, out, lout, workspace, workspace_bytes, stream);
+}
 
 fpe_status fpe_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* workspace,
                        size_t workspace_bytes, void* stream) {

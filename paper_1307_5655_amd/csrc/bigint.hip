@@ -1,0 +1,222 @@
+// Exact evaluation over the natural numbers at big-integer points: the
+// workload of the paper's Benchmarks section (Figure 1: the balanced scheme
+// against Estrin's over multiprecision integers).
+//
+// The walk is the stack program of the pointwise kernels with big-integer
+// accumulators, one wavefront per point (all points of a batch resident at
+// once, as in the composition kernel).  A big integer is an array of 16-bit
+// limbs (least significant first) held in 32-bit words, so a product of two
+// limbs fits in 32 bits and a column of up to 2^16 products fits in 64.  A
+// multiply-add out (+)= a b + c0 is a convolution over the wavefront (lane l
+// sums the columns l, l + 64, ...) into 64-bit columns, then one lane carries
+// the columns into limbs.  Coefficients are uint64 (four limbs); with
+// coefficients and points >= 0 every partial value is at most p(x), so every
+// value fits the output's limb count.
+#include <hip/hip_runtime.h>
+
+#include "fpe_internal.h"
+
+namespace fpe {
+
+namespace {
+
+constexpr int kLanes = 64;   // one wavefront per point
+
+__global__ void k_zero_flag(int32_t* p) { *p = 0; }
+
+inline int64_t align64(int64_t words) { return (words + 63) & ~int64_t(63); }
+
+// Per-point workspace (32-bit words): the stack buffers and the power table
+// (lout limbs each), then the 64-bit columns (2 lout words), 256-byte aligned.
+inline int64_t col_offset(const fpe_tree* t, int32_t lout) {
+  return align64((int64_t)(t->depth + 2 + t->n_table) * lout);
+}
+inline int64_t per_point_words(const fpe_tree* t, int32_t lout) {
+  return align64(col_offset(t, lout) + 2 * (int64_t)lout);
+}
+
+struct BigArgs {
+  DevTree tr;
+  const uint32_t* x;      // batch x lx limbs
+  uint32_t* out;          // batch x lout limbs
+  uint32_t* ws;           // batch x per_instance words
+  int32_t lx;
+  int32_t lout;           // limbs of every value (output capacity)
+  int64_t per_instance;   // words of workspace per point
+  int32_t nbuf;           // stack buffers (depth + 2)
+  int64_t col_off;        // words from the point's workspace to its 64-bit columns
+  int32_t* overflow;      // set if a value needs more than lout limbs (cannot happen
+                          // when lout is at least the host's bound)
+};
+
+// out[0 .. lout) (+)= a[0 .. la) * b[0 .. lb) + c0; returns the length of the
+// result (index of the highest nonzero limb + 1, at least 1).  col is 64-bit
+// scratch of lout words.  All lanes of the wavefront call it.
+__device__ int big_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uint32_t* out, int lout,
+                       bool accumulate, uint64_t c0, uint64_t* col, int32_t* overflow) {
+  const int lane = threadIdx.x;
+  const int lp = min(la + lb - 1, lout);
+  for (int k = lane; k < lout; k += kLanes) {
+    uint64_t s = 0;
+    if (k < lp) {
+      const int i0 = max(0, k - (lb - 1)), i1 = min(la - 1, k);
+      for (int i = i0; i <= i1; ++i) s += (uint64_t)a[i] * b[k - i];
+    }
+    if (accumulate) s += out[k];
+    if (k < 4) s += (c0 >> (16 * k)) & 0xFFFFu;
+    col[k] = s;
+  }
+  __syncthreads();
+  __shared__ int len_s;
+  if (lane == 0) {
+    uint64_t carry = 0;
+    int len = 1;
+    for (int k = 0; k < lout; ++k) {
+      carry += col[k];
+      const uint32_t limb = (uint32_t)(carry & 0xFFFFu);
+      out[k] = limb;
+      if (limb) len = k + 1;
+      carry >>= 16;
+    }
+    if (carry) *overflow = 1;
+    len_s = len;
+  }
+  __syncthreads();
+  return len_s;
+}
+
+__global__ __launch_bounds__(kLanes) void k_bigint_walk(BigArgs A) {
+  const int64_t inst = blockIdx.x;
+  const DevTree& tr = A.tr;
+  const int L = A.lout;
+  uint32_t* W = A.ws + inst * A.per_instance;
+  uint32_t* table = W + (int64_t)A.nbuf * L;                       // n_table values
+  uint64_t* col = (uint64_t*)(W + A.col_off);                      // 64-bit columns, L of them
+  const uint32_t* xi = A.x + inst * (int64_t)A.lx;
+  __shared__ int32_t tab_len[kMaxTable];
+  __shared__ int32_t buf[kMaxDepth + 2];
+  __shared__ int32_t len[kMaxDepth + 2];
+  __shared__ uint32_t one[4];   // a coefficient as four limbs
+
+  // powers x^d by the chain
+  for (int c = 0; c < tr.n_chain; ++c) {
+    const ChainStep st = tr.chain[c];
+    uint32_t* dst = table + (int64_t)st.dst * L;
+    if (!chain_is_mul(st.kind)) {
+      int lx = 1;
+      for (int k = 0; k < A.lx; ++k)
+        if (xi[k]) lx = k + 1;
+      for (int k = threadIdx.x; k < L; k += kLanes) dst[k] = k < A.lx ? xi[k] : 0u;
+      if (threadIdx.x == 0) tab_len[st.dst] = lx;
+    } else {
+      const int la = tab_len[st.s1], lb = tab_len[st.s2];
+      const int n = big_mac(table + (int64_t)st.s1 * L, la, table + (int64_t)st.s2 * L, lb, dst, L, false, 0,
+                            col, A.overflow);
+      if (threadIdx.x == 0) tab_len[st.dst] = n;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < kMaxDepth + 2) {
+    buf[threadIdx.x] = threadIdx.x;
+    len[threadIdx.x] = 1;
+  }
+  __syncthreads();
+
+  auto coef = [&](uint64_t c) {   // the four limbs of c, in LDS
+    if (threadIdx.x < 4) one[threadIdx.x] = (uint32_t)((c >> (16 * threadIdx.x)) & 0xFFFFu);
+    __syncthreads();
+  };
+  int top = 0;   // open accumulators (uniform)
+  for (int pc = 0; pc < tr.n_ops; ++pc) {
+    const OpF64 o = tr.ops64[pc];
+    const uint32_t kind = op_kind(o.info);
+    const uint32_t pidx = op_pidx(o.info);
+    const bool haspow = pidx != kOffTable;
+    const uint32_t* X = haspow ? table + (int64_t)pidx * L : nullptr;
+    const int lx = haspow ? tab_len[pidx] : 1;
+    if (kind == kLeafAdd) {                       // top += c(N) X
+      coef(o.a);
+      uint32_t* d = W + (int64_t)buf[top - 1] * L;
+      const int n = big_mac(one, 4, X, lx, d, L, true, 0, col, A.overflow);
+      if (threadIdx.x == 0) len[top - 1] = n;
+    } else if (kind == kNodeOpen) {               // top = top X + c(P)
+      uint32_t* s = W + (int64_t)buf[top - 1] * L;
+      uint32_t* d = W + (int64_t)buf[top] * L;   // free buffer above the top
+      const int n = big_mac(s, len[top - 1], X, lx, d, L, false, o.b, col, A.overflow);
+      if (threadIdx.x == 0) {
+        const int b = buf[top - 1];
+        buf[top - 1] = buf[top];
+        buf[top] = b;
+        len[top - 1] = n;
+      }
+    } else if (kind == kLeafOpen) {               // push c(N) X + c(P)
+      coef(o.a);
+      uint32_t* d = W + (int64_t)buf[top] * L;
+      const int n = big_mac(one, 4, X, lx, d, L, false, o.b, col, A.overflow);
+      if (threadIdx.x == 0) len[top] = n;
+      ++top;
+    } else if (kind == kNodeAdd) {                // below += top X; pop
+      uint32_t* s = W + (int64_t)buf[top - 1] * L;
+      uint32_t* d = W + (int64_t)buf[top - 2] * L;
+      const int n = big_mac(s, len[top - 1], X, lx, d, L, true, 0, col, A.overflow);
+      if (threadIdx.x == 0) len[top - 2] = n;
+      --top;
+    } else {                                      // END: y = (children ? top : c(R)) X_R
+      uint32_t* res = A.out + inst * (int64_t)L;
+      const bool leaf_root = (o.info & kEndLeafRoot) != 0;
+      const bool pw = (o.info & kEndHasPow) != 0;
+      if (leaf_root) {
+        coef(o.a);
+        if (pw) {
+          big_mac(one, 4, X, lx, res, L, false, 0, col, A.overflow);
+        } else {
+          for (int k = threadIdx.x; k < L; k += kLanes) res[k] = k < 4 ? one[k] : 0u;
+        }
+      } else {
+        const uint32_t* s = W + (int64_t)buf[top - 1] * L;
+        if (pw) big_mac(s, len[top - 1], X, lx, res, L, false, 0, col, A.overflow);
+        else
+          for (int k = threadIdx.x; k < L; k += kLanes) res[k] = s[k];
+      }
+      break;
+    }
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+size_t bigint_workspace_bytes(const fpe_tree* t, int32_t lout, int64_t batch) {
+  if (!t || lout < 1 || batch < 1) return 0;
+  // 256 bytes for the overflow flag, then every point's workspace
+  return 256 + (size_t)per_point_words(t, lout) * sizeof(uint32_t) * (size_t)batch;
+}
+
+fpe_status launch_bigint(const fpe_tree* t, const uint32_t* x, int32_t lx, int64_t batch, uint32_t* out,
+                         int32_t lout, void* ws, size_t ws_bytes, void* stream) {
+  if (t->n_offtable > 0) return fail(FPE_EUNSUPPORTED, "big-integer evaluation needs every power in the table");
+  if (t->depth + 2 > kMaxDepth + 2) return fail(FPE_EUNSUPPORTED, "walk deeper than the kernels hold");
+  if (batch < 1 || batch > 0x7fffffff) return fail(FPE_EINVAL, "batch out of range");
+  if (!ws || ws_bytes < bigint_workspace_bytes(t, lout, batch))
+    return fail(FPE_ENOMEM, "workspace smaller than fpe_bigint_workspace_bytes()");
+  if (((uintptr_t)ws) & 255) return fail(FPE_EINVAL, "workspace must be 256-byte aligned");
+  BigArgs A{};
+  A.tr = dev_view(t);
+  A.x = x;
+  A.out = out;
+  A.overflow = (int32_t*)ws;                       // first 256 bytes: the overflow flag
+  A.ws = (uint32_t*)((char*)ws + 256);
+  A.lx = lx;
+  A.lout = lout;
+  A.per_instance = per_point_words(t, lout);
+  A.col_off = col_offset(t, lout);
+  A.nbuf = t->depth + 2;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, st, A.overflow);
+  hipLaunchKernelGGL(k_bigint_walk, dim3((unsigned)batch), dim3(kLanes), 0, st, A);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("big-integer launch: ") + hipGetErrorString(e));
+  return FPE_OK;
+}
+
+}  // namespace fpe

@@ -339,8 +339,12 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
   if (nvars < 1 || nvars > 8) return fail(FPE_EINVAL, "nvars must be in 1..8");
   if (nterms < 1) return fail(FPE_EINVAL, "nterms must be >= 1");
   if (!exps || !coeffs || !fs) return fail(FPE_EINVAL, "NULL exps, coeffs or scheme");
-  if (domain != FPE_F64 && domain != FPE_F32C && domain != FPE_MODP && domain != FPE_IVAL)
+  if (domain != FPE_F64 && domain != FPE_F32C && domain != FPE_MODP && domain != FPE_IVAL &&
+      domain != FPE_BIGINT)
     return fail(FPE_EINVAL, "unknown domain");
+  if (domain == FPE_BIGINT && nvars != 1) return fail(FPE_EUNSUPPORTED, "big-integer evaluation is univariate");
+  // integer coefficients (uint64): residues mod p, or the big-integer walk's
+  const bool intcoef = domain == FPE_MODP || domain == FPE_BIGINT;
   if (batch < 1) return fail(FPE_EINVAL, "batch must be >= 1");
   if (domain != FPE_MODP && batch != 1) return fail(FPE_EINVAL, "batch > 1 needs FPE_MODP");
   if (domain == FPE_MODP && modulus != kP61 && modulus != kP31)
@@ -374,6 +378,8 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
         if (c >= modulus) return fail(FPE_EINVAL, "residue >= modulus");
         nz |= c != 0;
       }
+    } else if (domain == FPE_BIGINT) {
+      nz = cu[t] != 0;
     } else {
       if (!std::isfinite(cf[t])) return fail(FPE_EINVAL, "non-finite coefficient");
       nz = cf[t] != 0.0;
@@ -448,10 +454,10 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
 
   // coefficients in node order (junctions 0)
   std::vector<double> cnode(N, 0.0);
-  if (domain == FPE_MODP) t->coef_rows.assign(batch * N, 0);
+  if (intcoef) t->coef_rows.assign(batch * N, 0);
   for (int64_t id = 0; id < T; ++id) {
     int64_t i = pos[id];
-    if (domain == FPE_MODP) {
+    if (intcoef) {
       for (int64_t r = 0; r < batch; ++r) t->coef_rows[r * N + i] = cu[r * nterms + keep[id]];
     } else {
       cnode[i] = cf[keep[id]];
@@ -464,7 +470,7 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
   for (int64_t i = 0; i < N; ++i) {
     fpe_node& nd = t->nodes[i];
     std::memset(&nd, 0, sizeof nd);
-    if (domain == FPE_MODP) nd.coef.u = t->coef_rows[i];
+    if (intcoef) nd.coef.u = t->coef_rows[i];
     else nd.coef.f = cnode[i];
     nd.parent = (int32_t)par[i];
     const int32_t* me = &t->exps[i * nvars];
@@ -541,7 +547,7 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
   // range of the power when the interval contains 0, so its powers come only
   // from the table or, beyond it, are computed on the fly from the bounds.
   const bool index_ops = domain == FPE_MODP && modulus == kP31;
-  const bool no_products = index_ops || domain == FPE_IVAL;
+  const bool no_products = index_ops || domain == FPE_IVAL || domain == FPE_BIGINT;
   const int32_t cap = no_products ? kMaxTable : kTableCap;
   PowerPlan plan;
   if (no_products) {
@@ -646,7 +652,7 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
   // ---- walk program (stack form of the walk of Section 2.1)
   auto bits = [&](int64_t i) -> uint64_t {
     if (index_ops) return (uint64_t)i;
-    if (domain == FPE_MODP) return t->coef_rows[i];
+    if (intcoef) return t->coef_rows[i];
     uint64_t u;
     std::memcpy(&u, &cnode[i], 8);
     return u;

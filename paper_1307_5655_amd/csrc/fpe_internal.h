@@ -198,7 +198,11 @@ size_t eval_workspace_bytes(const fpe_tree* t, int64_t npts);
 fpe_status launch_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out,
                           void* ws, size_t ws_bytes, void* stream);
 size_t compose_workspace_bytes(const fpe_tree* t, int32_t dq);
+fpe_status launch_bigint(const fpe_tree* t, const uint32_t* x, int32_t lx, int64_t batch, uint32_t* out,
+                         int32_t lout, void* ws, size_t ws_bytes, void* stream);
+size_t bigint_workspace_bytes(const fpe_tree* t, int32_t lout, int64_t batch);
 constexpr int kMaxDepth = 15;   // stack depth the kernels hold (the code's 4-bit level field)
+constexpr int kBigMaxLimbs = 1 << 16;   // big-integer values: columns of 2^16 limb products fit in 64 bits
 constexpr int kMaxTable = 48;   // power-table entries held per point (composition)
 constexpr int kTableCap = 16;   // smallest table size the compiler tries
 constexpr int kTableCapMulti = 32;   // largest table of the kernels with several points per lane

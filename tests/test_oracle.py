@@ -396,3 +396,19 @@ def test_compose_schwartz_zippel_and_native():
         assert got[b].tolist() == r
         for t in [3, 1000003, p - 2]:
             assert ocomp.horner_at(r, t, p) == ocomp.compose_at(P[b].tolist(), Q[b].tolist(), t, p)
+
+
+def test_bigint_oracle_closed_forms_and_limbs():
+    """The big-integer oracle against closed forms: (x + 1)^n by the binomial
+    theorem and the geometric sum (x^(n+1) - 1) / (x - 1); limbs round trip."""
+    from oracle import bigint
+    g = np.random.default_rng(31)
+    for n in (1, 7, 64, 255):
+        x = int(g.integers(2, 2 ** 62)) * 2 ** 70 + 12345
+        binom = [((e,), math.comb(n, e)) for e in range(n + 1)]
+        assert bigint.eval_int(binom, x) == (x + 1) ** n
+        geo = [((e,), 1) for e in range(n + 1)]
+        assert bigint.eval_int(geo, x) * (x - 1) == x ** (n + 1) - 1
+        v = bigint.eval_int(geo, x)
+        nl = v.bit_length() // 16 + 1
+        assert bigint.from_limbs(bigint.to_limbs(v, nl)) == v
