@@ -239,6 +239,42 @@ def interval_phase(fpe, fpe_inputs, torch, dev, hev, npts: int, reps: int = 3):
     return res
 
 
+def bigint_phase(fpe, torch, dev, reps: int = 3):
+    """Exact evaluation over the natural numbers (the workload of the paper's
+    Benchmarks section): 64-bit coefficients, 256 points of 256 bits, dense
+    polynomials with term counts around powers of two; time per scheme and
+    the ratio to the balanced scheme (the form of the paper's Figure 1)."""
+    g = np.random.default_rng([13075655, 8])
+    lx, batch = 16, 256
+    x = torch.from_numpy(g.integers(0, 1 << 16, size=(batch, lx), dtype=np.int64).astype(np.int32)).to(dev)
+    res = {}
+    for n in (127, 128, 129, 255, 256, 257):
+        ex = np.arange(n + 1, dtype=np.int32).reshape(-1, 1)
+        co = g.integers(1, 2 ** 63, n + 1, dtype=np.uint64)
+        row = {}
+        for s in ("balanced", "estrin", "horner"):
+            t = fpe.Tree(ex, co, s, fpe.BIGINT).upload(dev)
+            lout = int(fpe.lib.fpe_bigint_out_limbs(t.handle, lx))
+            out = torch.empty((batch, lout), dtype=torch.int32, device=dev)
+            ws = torch.empty(int(fpe.lib.fpe_bigint_workspace_bytes(t.handle, lout, batch)) + 256, dtype=torch.uint8,
+                             device=dev)
+            fpe.eval_bigint(t, x, out=out, workspace=ws, lout=lout)
+            torch.cuda.synchronize()
+            ms = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fpe.eval_bigint(t, x, out=out, workspace=ws, lout=lout)
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            row[s] = float(np.median(ms))
+        res[f"terms{n + 1}"] = {"ms": row, "estrin_over_balanced": row["estrin"] / row["balanced"],
+                                "horner_over_balanced": row["horner"] / row["balanced"]}
+    return res
+
+
 def compose_phase(fpe, fpe_inputs, torch, dev, reps: int = 3):
     """4096 instances of p(q(x)) mod 2^31-1, deg p = 255, deg q = 15."""
     inp = fpe_inputs.compose_batch()
@@ -426,7 +462,7 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
-    served = latency = modp = compose = ival = None
+    served = latency = modp = compose = ival = big = None
     if not args.no_extra:
         log("served stream")
         served, latency = served_phase(fpe, fpe_inputs, torch, dev, args.served_requests, load=0.8)
@@ -436,6 +472,8 @@ def main():
         compose = compose_phase(fpe, fpe_inputs, torch, dev)
         log("interval")
         ival = interval_phase(fpe, fpe_inputs, torch, dev, hev, args.points)
+        log("big integers")
+        big = bigint_phase(fpe, torch, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -489,6 +527,7 @@ def main():
         "modp_trivariate": modp,
         "compose_4096": compose,
         "interval_1e7": ival,
+        "bigint_256bit_points": big,
     }
     print(json.dumps(out), flush=True)
 
