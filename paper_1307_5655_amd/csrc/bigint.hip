@@ -49,29 +49,47 @@ struct BigArgs {
                           // when lout is at least the host's bound)
 };
 
-// out[0 .. lout) (+)= a[0 .. la) * b[0 .. lb) + c0; returns the length of the
-// result (index of the highest nonzero limb + 1, at least 1).  col is 64-bit
-// scratch of lout words.  All lanes of the wavefront call it.
+// Operands up to kBigLds limbs are staged in LDS for the product (one
+// wavefront per workgroup, so the columns' reads do not wait on L2).
+constexpr int kBigLds = 4096;
+
+// out (+)= a[0 .. la) * b[0 .. lb) + c0, where out holds lacc limbs when
+// accumulating; returns the length of the result (index of the highest
+// nonzero limb + 1, at least 1).  Only the limbs below the result's length
+// bound max(la + lb, lacc, 4) + 2 are written: a value is read below its
+// length only.  col is 64-bit scratch of lout words.  All lanes call it.
 __device__ int big_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uint32_t* out, int lout,
-                       bool accumulate, uint64_t c0, uint64_t* col, int32_t* overflow) {
+                       bool accumulate, int lacc, uint64_t c0, uint64_t* col, int32_t* overflow) {
+  __shared__ uint32_t sa[kBigLds], sb[kBigLds];
+  __shared__ int len_s;
   const int lane = threadIdx.x;
   const int lp = min(la + lb - 1, lout);
-  for (int k = lane; k < lout; k += kLanes) {
+  // limbs the result can reach: the product, the accumulated value and the
+  // four limbs of c0, plus carries
+  const int nhi = min(max(max(la + lb, accumulate ? lacc : 0), 4) + 2, lout);
+  const bool staged = la <= kBigLds && lb <= kBigLds;
+  if (staged) {
+    for (int k = lane; k < la; k += kLanes) sa[k] = a[k];
+    for (int k = lane; k < lb; k += kLanes) sb[k] = b[k];
+    __syncthreads();
+  }
+  const uint32_t* A = staged ? sa : a;
+  const uint32_t* Bv = staged ? sb : b;
+  for (int k = lane; k < nhi; k += kLanes) {
     uint64_t s = 0;
     if (k < lp) {
       const int i0 = max(0, k - (lb - 1)), i1 = min(la - 1, k);
-      for (int i = i0; i <= i1; ++i) s += (uint64_t)a[i] * b[k - i];
+      for (int i = i0; i <= i1; ++i) s += (uint64_t)A[i] * Bv[k - i];
     }
-    if (accumulate) s += out[k];
+    if (accumulate && k < lacc) s += out[k];
     if (k < 4) s += (c0 >> (16 * k)) & 0xFFFFu;
     col[k] = s;
   }
   __syncthreads();
-  __shared__ int len_s;
   if (lane == 0) {
     uint64_t carry = 0;
     int len = 1;
-    for (int k = 0; k < lout; ++k) {
+    for (int k = 0; k < nhi; ++k) {
       carry += col[k];
       const uint32_t limb = (uint32_t)(carry & 0xFFFFu);
       out[k] = limb;
@@ -110,7 +128,7 @@ __global__ __launch_bounds__(kLanes) void k_bigint_walk(BigArgs A) {
       if (threadIdx.x == 0) tab_len[st.dst] = lx;
     } else {
       const int la = tab_len[st.s1], lb = tab_len[st.s2];
-      const int n = big_mac(table + (int64_t)st.s1 * L, la, table + (int64_t)st.s2 * L, lb, dst, L, false, 0,
+      const int n = big_mac(table + (int64_t)st.s1 * L, la, table + (int64_t)st.s2 * L, lb, dst, L, false, 0, 0,
                             col, A.overflow);
       if (threadIdx.x == 0) tab_len[st.dst] = n;
     }
@@ -137,12 +155,12 @@ __global__ __launch_bounds__(kLanes) void k_bigint_walk(BigArgs A) {
     if (kind == kLeafAdd) {                       // top += c(N) X
       coef(o.a);
       uint32_t* d = W + (int64_t)buf[top - 1] * L;
-      const int n = big_mac(one, 4, X, lx, d, L, true, 0, col, A.overflow);
+      const int n = big_mac(one, 4, X, lx, d, L, true, len[top - 1], 0, col, A.overflow);
       if (threadIdx.x == 0) len[top - 1] = n;
     } else if (kind == kNodeOpen) {               // top = top X + c(P)
       uint32_t* s = W + (int64_t)buf[top - 1] * L;
       uint32_t* d = W + (int64_t)buf[top] * L;   // free buffer above the top
-      const int n = big_mac(s, len[top - 1], X, lx, d, L, false, o.b, col, A.overflow);
+      const int n = big_mac(s, len[top - 1], X, lx, d, L, false, 0, o.b, col, A.overflow);
       if (threadIdx.x == 0) {
         const int b = buf[top - 1];
         buf[top - 1] = buf[top];
@@ -152,32 +170,39 @@ __global__ __launch_bounds__(kLanes) void k_bigint_walk(BigArgs A) {
     } else if (kind == kLeafOpen) {               // push c(N) X + c(P)
       coef(o.a);
       uint32_t* d = W + (int64_t)buf[top] * L;
-      const int n = big_mac(one, 4, X, lx, d, L, false, o.b, col, A.overflow);
+      const int n = big_mac(one, 4, X, lx, d, L, false, 0, o.b, col, A.overflow);
       if (threadIdx.x == 0) len[top] = n;
       ++top;
     } else if (kind == kNodeAdd) {                // below += top X; pop
       uint32_t* s = W + (int64_t)buf[top - 1] * L;
       uint32_t* d = W + (int64_t)buf[top - 2] * L;
-      const int n = big_mac(s, len[top - 1], X, lx, d, L, true, 0, col, A.overflow);
+      const int n = big_mac(s, len[top - 1], X, lx, d, L, true, len[top - 2], 0, col, A.overflow);
       if (threadIdx.x == 0) len[top - 2] = n;
       --top;
     } else {                                      // END: y = (children ? top : c(R)) X_R
       uint32_t* res = A.out + inst * (int64_t)L;
       const bool leaf_root = (o.info & kEndLeafRoot) != 0;
       const bool pw = (o.info & kEndHasPow) != 0;
+      int n = 4;                                  // limbs written below (the rest are zeroed)
       if (leaf_root) {
         coef(o.a);
         if (pw) {
-          big_mac(one, 4, X, lx, res, L, false, 0, col, A.overflow);
+          n = min(4 + lx + 2, L);
+          big_mac(one, 4, X, lx, res, L, false, 0, 0, col, A.overflow);
         } else {
-          for (int k = threadIdx.x; k < L; k += kLanes) res[k] = k < 4 ? one[k] : 0u;
+          for (int k = threadIdx.x; k < 4; k += kLanes) res[k] = one[k];
         }
       } else {
         const uint32_t* s = W + (int64_t)buf[top - 1] * L;
-        if (pw) big_mac(s, len[top - 1], X, lx, res, L, false, 0, col, A.overflow);
-        else
-          for (int k = threadIdx.x; k < L; k += kLanes) res[k] = s[k];
+        if (pw) {
+          n = min(len[top - 1] + lx + 2, L);
+          big_mac(s, len[top - 1], X, lx, res, L, false, 0, 0, col, A.overflow);
+        } else {
+          n = len[top - 1];
+          for (int k = threadIdx.x; k < n; k += kLanes) res[k] = s[k];
+        }
       }
+      for (int k = n + threadIdx.x; k < L; k += kLanes) res[k] = 0;
       break;
     }
     __syncthreads();
