@@ -49,9 +49,11 @@ struct BigArgs {
                           // when lout is at least the host's bound)
 };
 
-// Operands up to kBigLds limbs are staged in LDS for the product (one
-// wavefront per workgroup, so the columns' reads do not wait on L2).
-constexpr int kBigLds = 4096;
+// Each operand of up to kBigStage limbs is staged in LDS for the product,
+// and results of up to kBigCols limbs keep their columns in LDS for the carry
+// pass (one wavefront per workgroup: its reads would otherwise wait on L2).
+constexpr int kBigStage = 3072;
+constexpr int kBigCols = 4096;
 
 // out (+)= a[0 .. la) * b[0 .. lb) + c0, where out holds lacc limbs when
 // accumulating; returns the length of the result (index of the highest
@@ -60,21 +62,23 @@ constexpr int kBigLds = 4096;
 // length only.  col is 64-bit scratch of lout words.  All lanes call it.
 __device__ int big_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uint32_t* out, int lout,
                        bool accumulate, int lacc, uint64_t c0, uint64_t* col, int32_t* overflow) {
-  __shared__ uint32_t sa[kBigLds], sb[kBigLds];
+  __shared__ uint32_t sa[kBigStage], sb[kBigStage];
+  __shared__ uint64_t scol[kBigCols];
   __shared__ int len_s;
   const int lane = threadIdx.x;
   const int lp = min(la + lb - 1, lout);
   // limbs the result can reach: the product, the accumulated value and the
   // four limbs of c0, plus carries
   const int nhi = min(max(max(la + lb, accumulate ? lacc : 0), 4) + 2, lout);
-  const bool staged = la <= kBigLds && lb <= kBigLds;
-  if (staged) {
+  const bool stage_a = la <= kBigStage, stage_b = lb <= kBigStage;
+  if (stage_a)
     for (int k = lane; k < la; k += kLanes) sa[k] = a[k];
+  if (stage_b)
     for (int k = lane; k < lb; k += kLanes) sb[k] = b[k];
-    __syncthreads();
-  }
-  const uint32_t* A = staged ? sa : a;
-  const uint32_t* Bv = staged ? sb : b;
+  __syncthreads();
+  const uint32_t* A = stage_a ? sa : a;
+  const uint32_t* Bv = stage_b ? sb : b;
+  uint64_t* C = nhi <= kBigCols ? scol : col;
   for (int k = lane; k < nhi; k += kLanes) {
     uint64_t s = 0;
     if (k < lp) {
@@ -83,14 +87,29 @@ __device__ int big_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uin
     }
     if (accumulate && k < lacc) s += out[k];
     if (k < 4) s += (c0 >> (16 * k)) & 0xFFFFu;
-    col[k] = s;
+    C[k] = s;
   }
   __syncthreads();
   if (lane == 0) {
+    // columns are read eight at a time so their loads overlap
     uint64_t carry = 0;
     int len = 1;
-    for (int k = 0; k < nhi; ++k) {
-      carry += col[k];
+    int k = 0;
+    for (; k + 8 <= nhi; k += 8) {
+      uint64_t v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = C[k + u];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        carry += v[u];
+        const uint32_t limb = (uint32_t)(carry & 0xFFFFu);
+        out[k + u] = limb;
+        if (limb) len = k + u + 1;
+        carry >>= 16;
+      }
+    }
+    for (; k < nhi; ++k) {
+      carry += C[k];
       const uint32_t limb = (uint32_t)(carry & 0xFFFFu);
       out[k] = limb;
       if (limb) len = k + 1;
