@@ -10,8 +10,9 @@ and uploaded once, before the timed region.
 
 After the timed region (not part of ``value``): the accuracy of the last step
 against the CPU oracle on a sample; a served stream (Poisson arrivals of
-uneven evaluate requests through the continuous-batching server) for p50/p99
-latency; the exact mod 2^61-1 trivariate workload and the batched
+uneven evaluate requests through the continuous-batching server: 10^4
+requests, first all at once for the saturation rate, then at 0.5, 0.8 and 0.95
+times that rate) for p50/p99 latency; the exact mod 2^61-1 trivariate workload and the batched
 composition mod 2^31-1, each timed beside the main line; and the CPU oracle
 timed on a bounded sample of the step's workload.
 
@@ -116,17 +117,20 @@ def measured_traffic():
         return None
 
 
-def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, load: float):
+def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, loads=(0.5, 0.8, 0.95)):
     """Poisson arrivals of uneven evaluate requests (compensated FP32 with FP64
     fallback) through the server: first all at once to find the saturation
-    request rate, then arrivals at ``load`` times that rate for latency."""
-    reqs = fpe_inputs.served_stream(nreq, rate_per_s=1.0)   # unit-rate arrival times, rescaled below
+    request rate, then arrivals at each of ``loads`` times that rate for
+    latency.  The points of every request are a window of one resident pool."""
+    stream = fpe_inputs.served_stream_pooled(nreq, rate_per_s=1.0)   # unit-rate arrival times, rescaled below
+    pool = torch.from_numpy(stream.pool).to(dev)
     prepared = []
-    for r in reqs:
+    for r, off in zip(stream.requests, stream.offsets):
         m = r.poly
+        v, n = m.points.shape
         t = fpe.Tree(m.exps, m.coeffs, r.scheme, fpe.F32C).upload(dev)
-        pts = [torch.from_numpy(np.ascontiguousarray(m.points[j])).to(dev) for j in range(m.points.shape[0])]
-        out = torch.empty(m.points.shape[1], dtype=torch.float64, device=dev)
+        pts = [pool[j, off:off + n] for j in range(v)]
+        out = torch.empty(n, dtype=torch.float64, device=dev)
         prepared.append((r.arrival_s, t, pts, out, m))
     torch.cuda.synchronize()
     budget = 2 << 30
@@ -143,32 +147,36 @@ def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, load: float):
     st = srv.stats()
     sat = {"requests": nreq, "wall_s": wall_sat, "term_evals": st.term_evals,
            "term_evals_per_s": st.term_evals / wall_sat, "batches": st.batches,
-           "fallback_frac": st.fallback_frac, "df32_step_ops": step_ops}
+           "fallback_frac": st.fallback_frac, "df32_step_ops": step_ops,
+           "fp32_peak_frac_of_wall": step_ops / (wall_sat * FP32_VALU_PEAK)}
     srv.close()
     sat_rps = nreq / wall_sat
 
-    rate = load * sat_rps
-    scale = 1.0 / rate
-    srv = fpe.Server(hbm_budget=budget, max_inflight=64)
-    t0 = time.perf_counter()
-    for at, t, pts, out, _ in prepared:
-        target = t0 + at * scale
-        while True:
-            now = time.perf_counter()
-            if now >= target:
-                break
-            if target - now > 2e-4:
-                time.sleep((target - now) * 0.5)
-        srv.submit(t, pts, out, domain=fpe.F32C)
-    srv.drain()
-    wall = time.perf_counter() - t0
-    st = srv.stats()
-    lat = {"load": load, "rate_rps": rate, "requests": nreq, "p50_ms": st.p50_ms, "p99_ms": st.p99_ms,
-           "mean_ms": st.mean_ms, "batches": st.batches, "term_evals_per_s": st.term_evals / wall,
-           "fallback_frac": st.fallback_frac}
-    srv.close()
+    by_load = []
+    for load in loads:
+        rate = load * sat_rps
+        scale = 1.0 / rate
+        srv = fpe.Server(hbm_budget=budget, max_inflight=64)
+        t0 = time.perf_counter()
+        for at, t, pts, out, _ in prepared:
+            target = t0 + at * scale
+            while True:
+                now = time.perf_counter()
+                if now >= target:
+                    break
+                if target - now > 2e-4:
+                    time.sleep((target - now) * 0.5)
+            srv.submit(t, pts, out, domain=fpe.F32C)
+        srv.drain()
+        wall = time.perf_counter() - t0
+        st = srv.stats()
+        by_load.append({"load": load, "rate_rps": rate, "requests": nreq, "p50_ms": st.p50_ms,
+                        "p99_ms": st.p99_ms, "mean_ms": st.mean_ms, "batches": st.batches,
+                        "term_evals_per_s": st.term_evals / wall, "fallback_frac": st.fallback_frac})
+        srv.close()
+        log(f"served load {load}: p50 {st.p50_ms:.2f} ms, p99 {st.p99_ms:.2f} ms")
 
-    # every served result against the oracle on a sample of its points
+    # served results against the oracle on a sample of requests and points
     from oracle import exact
     worst = 0.0
     for _, _, _, out, m in prepared[:: max(1, nreq // 24)]:
@@ -176,7 +184,10 @@ def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, load: float):
         idx = np.arange(0, len(y), max(1, len(y) // 64))
         ref = exact.dd_monomial_sum(m.exps, m.coeffs, m.points[:, idx])
         worst = max(worst, float(np.max(np.abs(y[idx] - ref) / np.abs(ref))))
+    head = next(d for d in by_load if d["load"] == 0.8) if 0.8 in loads else by_load[-1]
+    lat = dict(head)
     lat["max_rel_err_sampled"] = worst
+    lat["other_loads"] = [d for d in by_load if d is not head]
     return sat, lat
 
 
@@ -311,7 +322,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-points", type=int, default=600_000)
     ap.add_argument("--no-extra", action="store_true", help="skip the served, mod-p and composition phases")
-    ap.add_argument("--served-requests", type=int, default=400)
+    ap.add_argument("--served-requests", type=int, default=10_000)
     ap.add_argument("--served-only", action="store_true",
                     help="run only the served stream (for a profiler run of the fused kernels) and print its results")
     ap.add_argument("--copy-probe", type=float, default=0,
@@ -330,7 +341,7 @@ def main():
 
     dev = torch.device("cuda:0")
     if args.served_only:
-        served, latency = served_phase(fpe, fpe_inputs, torch, dev, args.served_requests, load=0.8)
+        served, latency = served_phase(fpe, fpe_inputs, torch, dev, args.served_requests)
         print(json.dumps({"served": {"saturation": served, "poisson": latency}}), flush=True)
         return
     degrees = (3000, 5000)
@@ -465,7 +476,7 @@ def main():
     served = latency = modp = compose = ival = big = None
     if not args.no_extra:
         log("served stream")
-        served, latency = served_phase(fpe, fpe_inputs, torch, dev, args.served_requests, load=0.8)
+        served, latency = served_phase(fpe, fpe_inputs, torch, dev, args.served_requests)
         log("mod-p trivariate")
         modp = modp_phase(fpe, fpe_inputs, torch, dev, hev)
         log("composition")

@@ -224,3 +224,44 @@ def served_stream(nreq: int, rate_per_s: float, seed_k: int = 5,
         scheme = ["horner", "estrin", "balanced"][int(g.integers(0, 3))]
         out.append(Request(t, scheme, random_multi_f64(v, T, N, g)))
     return out
+
+
+@dataclass
+class PooledStream:
+    requests: list[Request]   # poly.points of each is a view of ``pool``
+    pool: np.ndarray          # float64 [3, P], U[-1, 1]
+    offsets: list[int]        # request k reads pool[:v, offsets[k]:offsets[k] + N]
+
+
+def served_stream_pooled(nreq: int, rate_per_s: float, pool_pts: int = 4_000_000, seed_k: int = 7,
+                         max_terms: int = 10_000, max_pts: int = 1_000_000,
+                         min_terms: int = 10, min_pts: int = 1_000) -> PooledStream:
+    """The served stream's request mix (as ``served_stream``) for long runs
+    (10^4 requests and more): each request's points are a window of one shared
+    pool of uniform points at a random offset, so the points of all requests
+    fit in a few arrays however many requests there are."""
+    assert pool_pts >= max_pts
+    g = rng_for(seed_k)
+    pool = g.uniform(-1.0, 1.0, size=(3, pool_pts))
+    mono = {}
+    t = 0.0
+    reqs, offs = [], []
+    for _ in range(nreq):
+        t += g.exponential(1.0 / rate_per_s)
+        v = int(g.integers(1, 4))
+        T = int(round(math.exp(g.uniform(math.log(min_terms), math.log(max_terms)))))
+        N = int(round(math.exp(g.uniform(math.log(min_pts), math.log(max_pts)))))
+        scheme = ["horner", "estrin", "balanced"][int(g.integers(0, 3))]
+        D = 0
+        while math.comb(D + v, v) < T:
+            D += 1
+        if (v, D) not in mono:
+            mono[(v, D)] = monomials_total_degree(v, D)
+        allm = mono[(v, D)]
+        ex = allm[np.sort(g.choice(len(allm), T, replace=False))]
+        co = g.uniform(-1.0, 1.0, T)
+        co[co == 0.0] = 0.5
+        off = int(g.integers(0, pool_pts - N + 1))
+        reqs.append(Request(t, scheme, MultiInput(ex, co, pool[:v, off:off + N])))
+        offs.append(off)
+    return PooledStream(reqs, pool, offs)
