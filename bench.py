@@ -137,6 +137,13 @@ def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, loads=(0.5, 0.8, 0.95))
     # FP32 operations of the compensated walks of one pass over the stream
     step_ops = float(sum(sum(k * o for k, o in zip(t.info.n_ops_kind, DF32_OPS_BY_KIND)) * m.points.shape[1]
                          for _, t, _, _, m in prepared))
+    # each request's ideal time on the roofline: the larger of its compensated
+    # walk's FP32 operations at the VALU peak and its point and result bytes
+    # (8 v + 8 per point) at the HBM peak
+    ideal_s = float(sum(max(sum(k * o for k, o in zip(t.info.n_ops_kind, DF32_OPS_BY_KIND)) * m.points.shape[1]
+                            / FP32_VALU_PEAK,
+                            (8 * m.points.shape[0] + 8) * m.points.shape[1] / (HBM_PEAK_GBS * 1e9))
+                        for _, t, _, _, m in prepared))
 
     srv = fpe.Server(hbm_budget=budget, max_inflight=64)
     t0 = time.perf_counter()
@@ -148,7 +155,8 @@ def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, loads=(0.5, 0.8, 0.95))
     sat = {"requests": nreq, "wall_s": wall_sat, "term_evals": st.term_evals,
            "term_evals_per_s": st.term_evals / wall_sat, "batches": st.batches,
            "fallback_frac": st.fallback_frac, "df32_step_ops": step_ops,
-           "fp32_peak_frac_of_wall": step_ops / (wall_sat * FP32_VALU_PEAK)}
+           "fp32_peak_frac_of_wall": step_ops / (wall_sat * FP32_VALU_PEAK),
+           "ideal_s": ideal_s, "roofline_frac_of_wall": ideal_s / wall_sat}
     srv.close()
     sat_rps = nreq / wall_sat
 
