@@ -274,10 +274,19 @@ fpe_status fpe_tree_deserialize(const void* buf, size_t bytes, fpe_tree** out) {
     if (op_kind(o.info) > kEnd || (p != kOffTable && p >= (uint32_t)t->n_table) ||
         (p2 != kNoPair && (p2 >= (uint32_t)t->n_table || p == kOffTable)) ||
         (p2 != kNoPair && (op_deg(o.deg) & kThirdBit) && (op_deg(o.deg) & 0xFFu) >= (uint32_t)t->n_table) ||
-        op_var(o.info) >= (uint32_t)t->nvars || (int)op_level(o.info) > kMaxDepth) {
+        op_var(o.info) >= (uint32_t)t->nvars || (int)op_level(o.info) > kMaxDepth ||
+        op_code(o.deg) != dispatch_code(o.info)) {
       delete t;
       return fail(FPE_EINVAL, "corrupt serialised tree (program)");
     }
+  }
+  // the FP32 records repeat the program of the FP64 ones
+  bool same = t->ops32.empty() || t->ops32.size() == t->ops64.size();
+  for (size_t k = 0; same && k < t->ops32.size(); ++k)
+    same = t->ops32[k].info == t->ops64[k].info && t->ops32[k].deg == t->ops64[k].deg;
+  if (!same || (t->domain == FPE_F32C) != !t->ops32.empty()) {
+    delete t;
+    return fail(FPE_EINVAL, "corrupt serialised tree (program)");
   }
   layout(t);
   *out = t;

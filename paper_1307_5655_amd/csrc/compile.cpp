@@ -662,7 +662,6 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
   for (int64_t i = 0; i < N; ++i) {
     const fpe_node& nd = t->nodes[i];
     OpF64 op{};
-    const int32_t depth_before = depth;
     uint32_t pidx2 = kNoPair, pidx3 = kNoPair;
     uint32_t pidx = nd.pdeg > 0 ? pidx_of(nd, pidx2, pidx3) : kOffTable;
     if (nd.pdeg > 0 && pidx == kOffTable) t->n_offtable++;
@@ -704,17 +703,8 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
     }
     op.info = info;
     t->n_kind[op_kind(info)]++;
-    {
-      // dispatch code: depth, kind, power class (END: depth 0, kind 0)
-      uint32_t pc = kPowOther;
-      if (pidx2 == kNoPair && pidx < (uint32_t)kRegPowers) pc = pidx;
-      else if (pidx2 == kNoPair && pidx != kOffTable) pc = kPowMem;
-      const uint32_t kind = op_kind(info);
-      const uint32_t lvl = (uint32_t)std::min(depth_before, 15);
-      const uint32_t code = kind == kEnd ? make_code(0, 0, (info & kEndHasPow) ? pc : kPowOther)
-                                         : make_code(lvl, kind, pc);
-      op.deg = (op.deg & 0xFFFFFu) | (code << 20);
-    }
+    // dispatch code: depth before the op, kind, power class (END: depth 0, kind 0)
+    op.deg = (op.deg & 0xFFFFFu) | (dispatch_code(info) << 20);
     t->ops64.push_back(op);
   }
   t->depth = std::max(maxd, 1);

@@ -56,17 +56,32 @@ __host__ __device__ inline uint32_t op_pidx2(uint32_t info) { return (info >> 25
 // The dispatch code of an op, in the top 12 bits of its deg field (the
 // partial degree itself, < 2^20, uses the low 20 bits): bits 0-3 the stack
 // depth L, bits 4-5 the kind (LEAF_ADD, NODE_OPEN, LEAF_OPEN, NODE_ADD),
-// bits 6-8 where its power comes from (0-3: register entry 0-3, 4: one entry
-// of the LDS tier or of the private table, 5: a product of two or three
-// entries, or computed on the fly).  LEAF_ADD at
-// depth 0 cannot occur, so codes with L = 0 and kind 0 mark the root (END).
+// bits 6-8 where its power comes from (0-3: register entry 0-3, 4: an entry
+// of the LDS tier, held in the private table by kernels without the tier,
+// 5: a product of two or three entries, or computed on the fly, 6: an entry
+// beyond the tier, in the private table).  Tier and private entries have
+// classes of their own so that a walk can read each with a plain LDS or
+// private load (with one class for both, the compiler selects the address
+// and issues a flat load).  LEAF_ADD at depth 0
+// cannot occur, so codes with L = 0 and kind 0 mark the root (END).
 constexpr int kRegPowers = 4;   // table entries kept in registers
 constexpr int kLdsPowers = 4;   // the next entries, kept in LDS (see walk_core.h)
-enum PowClass : uint32_t { kPowMem = 4, kPowOther = 5 };
+enum PowClass : uint32_t { kPowMem = 4, kPowOther = 5, kPowPriv = 6 };
 constexpr uint32_t make_code(uint32_t level, uint32_t kind, uint32_t pclass) {
   return (level & 15u) | (kind << 4) | (pclass << 6);
 }
 __host__ __device__ inline uint32_t op_code(uint32_t deg) { return deg >> 20; }
+// The dispatch code of an op from its info word (whose level field holds the
+// stack depth before the op).
+__host__ __device__ inline uint32_t dispatch_code(uint32_t info) {
+  const uint32_t p = op_pidx(info), p2 = op_pidx2(info), kind = op_kind(info);
+  uint32_t pc = kPowOther;
+  if (p2 == kNoPair && p < (uint32_t)kRegPowers) pc = p;
+  else if (p2 == kNoPair && p != kOffTable) pc = p < (uint32_t)(kRegPowers + kLdsPowers) ? kPowMem : kPowPriv;
+  if (kind == kEnd) return make_code(0, 0, (info & kEndHasPow) ? pc : kPowOther);
+  const uint32_t lvl = op_level(info);
+  return make_code(lvl < 15u ? lvl : 15u, kind, pc);
+}
 __host__ __device__ inline uint32_t op_deg(uint32_t deg) { return deg & 0xFFFFFu; }
 
 struct alignas(32) OpF64 {   // FP64 / double-double / mod-p walks

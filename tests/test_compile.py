@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 from hypothesis import given, settings, strategies as st
 
+import fpe_inputs
 import paper_1307_5655_amd as fpe
 from oracle import schemes, tree
 
@@ -182,6 +183,45 @@ def test_serialize_roundtrip():
     bad[0] ^= 0xFF
     with pytest.raises(fpe.FpeError):
         fpe.Tree.deserialize(bytes(bad))
+
+
+def _op_arrays(blob, n):
+    """Byte offsets of the FP64 and FP32 op records (n of each, 32 bytes) in a
+    serialised compensated-FP32 tree: each array follows its u64 length, the
+    FP32 one right after the FP64 one, and both carry the same info and deg
+    words at bytes 16-23 of each record."""
+    u64 = lambda q: int.from_bytes(blob[q:q + 8], "little")
+    hits = []
+    for q in range(0, len(blob) - 16 - 64 * n):
+        if u64(q) == n and u64(q + 8 + 32 * n) == n:
+            a, b = q + 8, q + 16 + 32 * n
+            if all(blob[a + 32 * k + 16:a + 32 * k + 24] == blob[b + 32 * k + 16:b + 32 * k + 24] for k in range(n)):
+                hits.append((a, b))
+    assert len(hits) == 1
+    return hits[0]
+
+
+def test_deserialize_checks_the_dispatch_codes():
+    """A serialised program whose dispatch code disagrees with its record (the
+    code selects the kernel's load of the power), or whose FP32 records differ
+    from the FP64 ones, is refused."""
+    inp = fpe_inputs.sparse_uni(3000, npts=1)
+    e = np.nonzero(inp.coeffs)[0]
+    t = fpe.Tree(e.astype(np.int32).reshape(-1, 1), inp.coeffs[e], "balanced", fpe.F32C)
+    assert t.info.n_table > 8          # entries in registers, in the LDS tier and beyond it
+    blob = t.serialize()
+    a, b = _op_arrays(blob, len(t.nodes()))
+    fpe.Tree.deserialize(blob)
+    codes = [int.from_bytes(blob[a + 32 * k + 20:a + 32 * k + 24], "little") >> 26 for k in range(len(t.nodes()))]
+    assert {4, 6} <= set(codes)        # power classes: LDS-tier and private entries
+    k = codes.index(6)
+    for arrays in ((a, b), (b,)):
+        bad = bytearray(blob)
+        for base in arrays:            # private-table class -> LDS-tier class
+            w = int.from_bytes(bad[base + 32 * k + 20:base + 32 * k + 24], "little")
+            bad[base + 32 * k + 20:base + 32 * k + 24] = (w ^ (2 << 26)).to_bytes(4, "little")
+        with pytest.raises(fpe.FpeError):
+            fpe.Tree.deserialize(bytes(bad))
 
 
 def test_library_exports_every_declared_symbol():
