@@ -204,6 +204,23 @@ size_t fpe_workspace_bytes(const fpe_tree* t, int64_t npts);
 fpe_status fpe_evaluate(const fpe_tree* t, const void* const* pts, int64_t npts, void* out,
                         const fpe_eval_opts* opts, void* stream);
 
+/* Allocation-free evaluation, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as fpe_evaluate, except
+ * that FPE_F32C takes its scratch (the fallback counter and the list of
+ * flagged point indices, 256 + 4 * FPE_NOALLOC_MAX_POINTS bytes) from a
+ * static device array of the library instead of opts->workspace (ignored).
+ * The array is zeroed where needed by the call itself (a kernel, no memset);
+ * each GPU holds its own copy until the process ends, looked up on the first
+ * call made with that device current.  The call allocates nothing (no
+ * hipMalloc, no library allocator).  Calls on one GPU share its array, so
+ * calls that overlap on one GPU (different streams, or several host
+ * threads) race and must be serialised by the caller.
+ * Errors: as fpe_evaluate; FPE_EINVAL if npts > FPE_NOALLOC_MAX_POINTS. */
+#define FPE_NOALLOC_MAX_POINTS (1 << 22)
+fpe_status fpe_evaluate_noalloc(const fpe_tree* t, const void* const* pts, int64_t npts, void* out,
+                                const fpe_eval_opts* opts, void* stream);
+
 /* Composition over Z/(2^31 - 1): for every instance r of the batch compiled into t
  * (univariate, FPE_MODP, modulus 2^31 - 1), out[r] = p_r(q_r(x)).
  *   q    device uint32[batch * (dq + 1)], coefficient j of instance r at r*(dq+1)+j, < p

@@ -101,6 +101,7 @@ def _load():
         "fpe_tree_deserialize": ([P, sz, ctypes.POINTER(P)], i32),
         "fpe_workspace_bytes": ([P, i64], sz),
         "fpe_evaluate": ([P, P, i64, P, ctypes.POINTER(EvalOpts), P], i32),
+        "fpe_evaluate_noalloc": ([P, P, i64, P, ctypes.POINTER(EvalOpts), P], i32),
         "fpe_compose_workspace_bytes": ([P, i32], sz),
         "fpe_compose": ([P, P, i32, P, P, sz, P], i32),
         "fpe_server_create": ([sz, i32, P, ctypes.POINTER(P)], i32),
@@ -126,6 +127,7 @@ lib = _load()
 EXPORTED = ["fpe_last_error", "fpe_version", "fpe_compile", "fpe_tree_free", "fpe_tree_nodes",
             "fpe_tree_get_info", "fpe_tree_node_exps", "fpe_tree_device_bytes", "fpe_tree_upload",
             "fpe_tree_serialize", "fpe_tree_deserialize", "fpe_workspace_bytes", "fpe_evaluate",
+            "fpe_evaluate_noalloc",
             "fpe_compose_workspace_bytes", "fpe_compose", "fpe_server_create", "fpe_server_submit",
             "fpe_server_poll", "fpe_server_wait", "fpe_server_drain", "fpe_server_stats",
             "fpe_server_destroy", "fpe_bigint_out_limbs", "fpe_bigint_workspace_bytes", "fpe_eval_bigint"]
@@ -297,6 +299,36 @@ def evaluate(tree: Tree, pts, out=None, tol: float = 1e-12, force: int = 0, cond
         opts.workspace_bytes = workspace.numel() - off
     _check(lib.fpe_evaluate(tree.handle, arr, npts, ctypes.c_void_p(out.data_ptr()),
                             ctypes.byref(opts), _stream_ptr(stream)))
+    return out
+
+
+NOALLOC_MAX_POINTS = 1 << 22
+
+
+def evaluate_noalloc(tree: Tree, pts, out, tol: float = 1e-12, force: int = 0, cond_out=None,
+                     flags_out=None, nfallback_out=None, stream=None):
+    """fpe_evaluate_noalloc: like ``evaluate`` with a caller-given ``out``, but
+    the compensated form's scratch is the library's static device array
+    (nothing is allocated by this call, here or in the library)."""
+    if tree._dev is None:
+        raise FpeError(-1, "tree is not uploaded")
+    pts = list(pts) if isinstance(pts, (list, tuple)) else [pts]
+    if len(pts) != tree.nvars:
+        raise FpeError(-1, f"{tree.nvars} point arrays expected, {len(pts)} given")
+    npts = pts[0].shape[0] if tree.domain == IVAL else pts[0].numel()
+    shape = (npts, 2) if tree.domain == IVAL else (npts,)
+    for p in pts:
+        if tuple(p.shape) != shape or not p.is_contiguous() or p.element_size() != 8:
+            raise FpeError(-1, f"point arrays must be contiguous 8-byte tensors of shape {shape}")
+    if out.numel() < (2 * npts if tree.domain == IVAL else npts) or not out.is_contiguous() \
+            or out.element_size() != 8:
+        raise FpeError(-1, "output must be a contiguous 8-byte tensor with a value (or interval) per point")
+    arr = (ctypes.c_void_p * 8)(*[p.data_ptr() for p in pts])
+    opts = EvalOpts(tol, force, 0, cond_out.data_ptr() if cond_out is not None else None,
+                    flags_out.data_ptr() if flags_out is not None else None, None, 0,
+                    nfallback_out.data_ptr() if nfallback_out is not None else None)
+    _check(lib.fpe_evaluate_noalloc(tree.handle, arr, npts, ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.byref(opts), _stream_ptr(stream)))
     return out
 
 

@@ -1,6 +1,8 @@
 // Host-side launch of the pointwise walks (fpe_evaluate): picks the kernel
 // by domain, walk depth, points per lane and whether any power is computed
 // on the fly; the kernels' launchers size the LDS tier of the power tables.
+#include <mutex>
+
 #include "walk_core.h"
 
 namespace fpe {
@@ -99,3 +101,74 @@ fpe_status launch_eval(const fpe_tree* t, const void* const* pts, int64_t npts, 
 }
 
 }  // namespace fpe
+
+// ----------------------------------------------------------------------------
+// Allocation-free evaluation (fpe_evaluate_noalloc).
+//
+// The compensated form needs a scratch buffer beyond the caller's inputs and
+// outputs: the fallback counter and the list of flagged point indices.  This
+// entry point takes it from a file-scope device array instead of a
+// workspace argument, so it calls no allocator.  Each GPU the library runs
+// on holds its own copy of the array (at its own address) until the process
+// ends.  In host code the array's name is only a stand-in for the device
+// symbol: its device address is looked up once per device with
+// hipGetSymbolAddress and only that address is handed to kernels.
+// ----------------------------------------------------------------------------
+
+namespace fpe {
+namespace {
+
+constexpr int64_t kNoAllocScratchBytes = 256 + (int64_t)sizeof(int32_t) * FPE_NOALLOC_MAX_POINTS;
+static __device__ __align__(256) char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this device's copy of the scratch array (looked up
+// on the first call on each device, with that device current).
+fpe_status scratch_address(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("hipGetDevice: ") + hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return fail(FPE_EUNSUPPORTED, "device index beyond the scratch table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(FPE_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return FPE_OK;
+}
+
+}  // namespace
+}  // namespace fpe
+
+extern "C" fpe_status fpe_evaluate_noalloc(const fpe_tree* t, const void* const* pts, int64_t npts, void* out,
+                                           const fpe_eval_opts* opts, void* stream) {
+  using namespace fpe;
+  if (!t) return fail(FPE_EINVAL, "tree is NULL");
+  if (!t->dev) return fail(FPE_EINVAL, "tree is not uploaded");
+  if (npts < 0) return fail(FPE_EINVAL, "npts < 0");
+  if (t->batch != 1) return fail(FPE_EINVAL, "a batch tree is for fpe_compose");
+  if (t->domain == FPE_BIGINT) return fail(FPE_EINVAL, "a big-integer tree is evaluated by fpe_eval_bigint");
+  if (npts > FPE_NOALLOC_MAX_POINTS)
+    return fail(FPE_EINVAL, "npts exceeds FPE_NOALLOC_MAX_POINTS, the allocation-free maximum");
+  if (npts == 0) return FPE_OK;
+  if (!pts || !out) return fail(FPE_EINVAL, "NULL points or output");
+  for (int j = 0; j < t->nvars; ++j)
+    if (!pts[j]) return fail(FPE_EINVAL, "NULL point array");
+  fpe_eval_opts o{};
+  if (opts) o = *opts;
+  if (t->domain == FPE_F32C) {
+    void* p = nullptr;
+    fpe_status st = scratch_address(&p);
+    if (st != FPE_OK) return st;
+    o.workspace = p;
+    o.workspace_bytes = (size_t)kNoAllocScratchBytes;
+  }
+  return launch_eval(t, pts, npts, out, &o, stream);
+}
