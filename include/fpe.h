@@ -181,6 +181,10 @@ typedef struct {
   int64_t* nfallback_out;   /* optional device int64: number of re-evaluated points (FPE_F32C) */
   void* ev_walk_begin;      /* optional hipEvent_t recorded on the stream right before the walk kernel */
   void* ev_walk_end;        /* optional hipEvent_t recorded right after it (before any fallback) */
+  double* bound_out;        /* optional device double[npts] (FPE_F32C): the error bound of the
+                               compensated walk that the fallback test compared with tol*|y|
+                               (its running relative terms plus its absolute part); a point
+                               not re-evaluated has |y - p(x)| <= bound_out[i] */
 } fpe_eval_opts;
 
 /* Workspace needed by fpe_evaluate for npts points (0 unless FPE_F32C). */

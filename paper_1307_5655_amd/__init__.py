@@ -58,7 +58,8 @@ class EvalOpts(ctypes.Structure):
                 ("points_per_lane", ctypes.c_int32), ("cond_out", ctypes.c_void_p),
                 ("flags_out", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("nfallback_out", ctypes.c_void_p),
-                ("ev_walk_begin", ctypes.c_void_p), ("ev_walk_end", ctypes.c_void_p)]
+                ("ev_walk_begin", ctypes.c_void_p), ("ev_walk_end", ctypes.c_void_p),
+                ("bound_out", ctypes.c_void_p)]
 
 
 class Request(ctypes.Structure):
@@ -259,7 +260,7 @@ def workspace_bytes(tree: Tree, npts: int) -> int:
 
 def evaluate(tree: Tree, pts, out=None, tol: float = 1e-12, force: int = 0, cond_out=None,
              flags_out=None, workspace=None, nfallback_out=None, stream=None, events=None,
-             points_per_lane: int = 0):
+             points_per_lane: int = 0, bound_out=None):
     """Evaluate ``tree`` at device points ``pts`` (list of tensors, one per
     variable: 1-D float64, or uint64 residues stored as int64 for FPE_MODP;
     for FPE_IVAL [npts, 2] float64 intervals (lo, hi), and the result is
@@ -286,6 +287,10 @@ def evaluate(tree: Tree, pts, out=None, tol: float = 1e-12, force: int = 0, cond
     opts = EvalOpts(tol, force, points_per_lane, cond_out.data_ptr() if cond_out is not None else None,
                     flags_out.data_ptr() if flags_out is not None else None, None, 0,
                     nfallback_out.data_ptr() if nfallback_out is not None else None)
+    if bound_out is not None:
+        if bound_out.numel() < npts or not bound_out.is_contiguous() or bound_out.element_size() != 8:
+            raise FpeError(-1, "bound_out must be a contiguous float64 tensor with a value per point")
+        opts.bound_out = bound_out.data_ptr()
     if events is not None:
         # raw hipEvent_t handles (ctypes.c_void_p or int)
         opts.ev_walk_begin = getattr(events[0], "value", events[0])

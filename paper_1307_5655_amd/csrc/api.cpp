@@ -16,6 +16,16 @@ namespace {
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
 void layout(fpe_tree* t) {
+  // bound data of the compensated walk, from the node array
+  for (int j = 0; j < 8; ++j) t->deg_max[j] = 0;
+  double c1 = 0;
+  for (size_t i = 0; i < t->nodes.size(); ++i) {
+    for (int j = 0; j < t->nvars; ++j) t->deg_max[j] = std::max(t->deg_max[j], t->exps[i * t->nvars + j]);
+    if (t->domain == FPE_F32C) c1 += std::fabs(t->nodes[i].coef.f);
+  }
+  // the FP64 sum of n non-negative terms is within n 2^-53 of the exact one
+  c1 *= 1.0 + (double)(t->nodes.size() + 1) * std::ldexp(1.0, -52);
+  t->abs_scale = df32_abs_scale((int64_t)t->ops64.size(), c1);
   size_t off = 0;
   // each op array is followed by kOpTail zero records (the walk reads ahead)
   t->off_ops64 = off;
@@ -46,6 +56,8 @@ DevTree dev_view(const fpe_tree* t) {
   d.n_offtable = t->n_offtable;
   d.bound_scale = df32_bound_scale(d.n_ops);
   d.batch = t->batch;
+  d.abs_scale = t->abs_scale;
+  for (int j = 0; j < 8; ++j) d.deg_max[j] = t->deg_max[j];
   return d;
 }
 

@@ -29,11 +29,14 @@ void k_eval_df32(DevTree tr, Pts<double> P, int64_t npts, F32COut o) {
     const int64_t i = base + (int64_t)j * kWave;
     bool flag = false;
     if (i < npts) {
-      double y;
+      // the coordinates are read again here rather than kept live across the walk
+      const double eabs = df32_abs_bound(tr, [&](int v) { return P.p[v][i]; });
+      double y, bnd;
       float cond;
-      flag = df32_finish<COND>(r[j], o.tol, tr.bound_scale, o.force, y, cond);
+      flag = df32_finish<COND>(r[j], eabs, o.tol, tr.bound_scale, o.force, y, cond, bnd);
       o.out[i] = y;
       if constexpr (COND) o.cond[i] = cond;
+      if (o.bound) o.bound[i] = bnd;
     }
     if (o.flags) {
       const uint64_t ballot = __ballot(flag);

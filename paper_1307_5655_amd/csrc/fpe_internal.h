@@ -136,6 +136,10 @@ struct DevTree {
   int32_t n_offtable;          // walk steps whose power is computed on the fly
   float bound_scale;           // double-float walk: factor on the final error bound
   int64_t batch;
+  // double-float walk: the absolute part of the error bound is
+  // abs_scale * prod_j max(1, |x_j|)^deg_max[j] (see df32_abs_bound)
+  double abs_scale;
+  int32_t deg_max[8];
 };
 
 // Work-table entry of a fused (served) launch: one request.  Its points are
@@ -188,6 +192,10 @@ struct fpe_tree {
   int32_t n_offtable = 0;
   int32_t n_pairs = 0;
   int32_t n_kind[5] = {};   // walk ops by OpKind
+  // derived from the node array by layout(): the largest exponent of each
+  // variable and the compensated walk's absolute bound scale
+  int32_t deg_max[8] = {};
+  double abs_scale = 0;
   // device image
   void* dev = nullptr;
   size_t off_ops64 = 0, off_ops32 = 0, off_chain = 0, off_coef = 0, dev_bytes = 0;
@@ -202,6 +210,16 @@ inline float df32_bound_scale(int64_t n_steps) {
   float f = (float)g;
   if ((double)f < g) f = std::nextafter(f, INFINITY);
   return f;
+}
+// Scale of the absolute part of the double-float walk's error bound, for a
+// tree of n_steps walk steps whose coefficients have 1-norm c1: every step
+// may lose up to 2^-147 to roundings in the subnormal range and to the split
+// of its constants, plus 2^-148 |a| to a power below the normal range (|a| the
+// multiplicand); carried up the tree, the powers scale these by at most
+// prod_j max(1, |x_j|)^deg_max[j], and |a| times those powers by at most c1
+// times it.  2^-145 (1 + c1) per step leaves a factor 2 of margin; rounded up.
+inline double df32_abs_scale(int64_t n_steps, double c1) {
+  return (double)n_steps * std::ldexp(1.0, -145) * (1.0 + c1) * (1.0 + std::ldexp(1.0, -30));
 }
 void set_error(const std::string& msg);
 fpe_status fail(fpe_status st, const std::string& msg);

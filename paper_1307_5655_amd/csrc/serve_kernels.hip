@@ -54,9 +54,10 @@ void k_serve_walk(WorkTable* wt) {
       else if (DMAX > 2 && it.tree.depth <= 2) rr = walk_point<ArDF32, 2, false>(it.tree, x, lds);
       else rr = walk_point<ArDF32, DMAX, false>(it.tree, x, lds);
       if (in) {
-        double y;
+        const double eabs = df32_abs_bound(it.tree, [&](int v) { return it.pts[v][i]; });
+        double y, bnd;
         float cond;
-        flag = df32_finish<true>(rr, it.tol, it.tree.bound_scale, 0, y, cond);
+        flag = df32_finish<true>(rr, eabs, it.tol, it.tree.bound_scale, 0, y, cond, bnd);
         it.out[i] = y;
         if (it.cond) it.cond[i] = cond;
       }

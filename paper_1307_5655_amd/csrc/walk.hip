@@ -76,6 +76,7 @@ fpe_status launch_eval(const fpe_tree* t, const void* const* pts, int64_t npts, 
     o.out = (double*)out;
     o.cond = opts->cond_out;
     o.flags = opts->flags_out;
+    o.bound = opts->bound_out;
     o.count = (int64_t*)opts->workspace;
     o.list = (int32_t*)((char*)opts->workspace + 256);
     o.tol = opts->tol > 0 ? opts->tol : 1e-12;

@@ -932,20 +932,39 @@ struct F32COut {
   uint32_t* flags;       // optional bitmask, 32 points per word
   int32_t* list;         // fallback indices
   int64_t* count;        // fallback count (device)
+  double* bound;         // optional: the error bound the test used, per point
   double tol;
   int32_t force;
 };
 
+// The absolute part of the double-float walk's error bound at point x (the
+// relative per-step terms assume normal FP32 numbers; this covers roundings
+// in the subnormal range, constants split below the normal range and
+// powers that underflow, carried up the tree): abs_scale times
+// prod_j max(1, |x_j|)^deg_max[j], with pow's rounding covered by a
+// 2^-40 margin.  A NaN coordinate gives NaN, and the point is flagged.
+template <class X>
+__device__ __forceinline__ double df32_abs_bound(const DevTree& tr, X&& xv) {
+  double m = tr.abs_scale;
+  for (int v = 0; v < tr.nvars; ++v) {
+    const double a = fabs(xv(v));
+    if (!(a <= 1.0) && tr.deg_max[v] > 0) m *= pow(a, (double)tr.deg_max[v]) * (1.0 + 0x1p-40);
+  }
+  return m;
+}
+
 // The result hi + lo in FP64 and whether it must be re-evaluated: the bound
-// does not certify tol relative accuracy, or a component is not finite.  The
-// decision does not use the condition sum, so it is the same whether or not
-// COND (the condition number p~(|x|) / |y| as output) is computed.
+// (running relative terms times the tree's scale, plus the absolute part
+// eabs) does not certify tol relative accuracy, or a component is not
+// finite.  The decision does not use the condition sum, so it is the same
+// whether or not COND (the condition number p~(|x|) / |y| as output) is
+// computed.
 template <bool COND>
-__device__ __forceinline__ bool df32_finish(const DF& r, double tol, float scale, int force, double& y,
-                                            float& cond) {
+__device__ __forceinline__ bool df32_finish(const DF& r, double eabs, double tol, float scale, int force,
+                                            double& y, float& cond, double& bound) {
   y = (double)r.h + (double)r.l;
   const double ay = fabs(y);
-  const double bound = (double)r.e * (double)scale;
+  bound = (double)r.e * (double)scale + eabs;
   const bool finite = isfinite(r.h) && isfinite(r.l) && isfinite(r.e);
   if constexpr (COND) cond = (float)((double)r.t / ay);
   bool flag = !finite || !(bound <= tol * ay) || ay < 1e-30;
