@@ -292,6 +292,45 @@ fpe_status fpe_tree_deserialize(const void* buf, size_t bytes, fpe_tree** out) {
       return fail(FPE_EINVAL, "corrupt serialised tree (program)");
     }
   }
+  // domain, modulus, batch and the coefficient rows agree: the composition
+  // kernel indexes coef_rows by instance and node, the modular walks take
+  // residues below the modulus
+  const bool intcoef = t->domain == FPE_MODP || t->domain == FPE_BIGINT;
+  bool meta = t->domain >= FPE_F64 && t->domain <= FPE_BIGINT && t->batch >= 1 && t->n_terms >= 1 &&
+              t->n_terms <= (int64_t)t->nodes.size() && t->table_var.size() == (size_t)t->n_table &&
+              t->table_deg.size() == (size_t)t->n_table;
+  if (meta && t->domain == FPE_MODP) meta = t->modulus == kP61 || t->modulus == kP31;
+  if (meta && t->domain != FPE_MODP) meta = t->modulus == 0;
+  if (meta && t->batch != 1) meta = t->domain == FPE_MODP && t->modulus == kP31;
+  if (meta && t->batch > ((int64_t)1 << 40) / (int64_t)std::max<size_t>(t->nodes.size(), 1)) meta = false;
+  if (meta) meta = t->coef_rows.size() == (intcoef ? (size_t)t->batch * t->nodes.size() : 0);
+  if (meta && t->domain == FPE_MODP)
+    for (uint64_t c : t->coef_rows)
+      if (c >= t->modulus) { meta = false; break; }
+  for (size_t k = 0; meta && k < t->exps.size(); ++k) meta = t->exps[k] >= 0 && t->exps[k] < (1 << 20);
+  if (!meta) {
+    delete t;
+    return fail(FPE_EINVAL, "corrupt serialised tree (domain, batch or coefficients)");
+  }
+  // the counts the launchers select kernels by are recounted from the
+  // program: on-the-fly powers (kernels without that path would read a table
+  // entry that does not exist), products of entries, steps by kind; a
+  // composition program's constants are node indices into the rows
+  int32_t offt = 0, pairs = 0, kinds[5] = {0, 0, 0, 0, 0};
+  const bool index_ops = t->domain == FPE_MODP && t->modulus == kP31;
+  for (const auto& o : t->ops64) {
+    const uint32_t kind = op_kind(o.info);
+    const bool haspow = kind != kEnd || (o.info & kEndHasPow);
+    if (haspow && op_pidx(o.info) == kOffTable) ++offt;
+    if (op_pidx2(o.info) != kNoPair) ++pairs;
+    ++kinds[kind];
+    if (index_ops && (o.a >= t->nodes.size() || o.b >= t->nodes.size())) offt = -1;
+  }
+  if (offt != t->n_offtable || pairs != t->n_pairs) {
+    delete t;
+    return fail(FPE_EINVAL, "corrupt serialised tree (power counts or node indices)");
+  }
+  for (int k = 0; k < 5; ++k) t->n_kind[k] = kinds[k];
   // the FP32 records repeat the program of the FP64 ones
   bool same = t->ops32.empty() || t->ops32.size() == t->ops64.size();
   for (size_t k = 0; same && k < t->ops32.size(); ++k)

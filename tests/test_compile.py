@@ -276,3 +276,56 @@ def test_tree_info_reports_domain_modulus_and_batch():
     assert (t.info.domain, t.info.modulus, t.info.batch) == (fpe.MODP, fpe.P31, 2)
     back = fpe.Tree.deserialize(t.serialize())
     assert (back.domain, back.modulus, back.batch) == (fpe.MODP, fpe.P31, 2)
+
+
+def _hdr_field(blob, off, fmt):
+    import struct
+    return struct.unpack_from(fmt, blob, off)[0]
+
+
+def _set_field(blob, off, fmt, v):
+    import struct
+    b = bytearray(blob)
+    struct.pack_into(fmt, b, off, v)
+    return bytes(b)
+
+
+# byte offsets of the serialised header: magic, nvars, domain, modulus,
+# batch, n_terms, n_table, n_powers, depth, max_slot, max_lh, n_offtable, n_pairs
+_OFF_BATCH, _OFF_NOFFT, _OFF_NPAIRS, _OFF_MOD, _OFF_DOMAIN = 24, 60, 64, 16, 12
+
+
+def test_deserialize_rejects_corrupt_counts_and_batch():
+    """Fields that select kernels or drive device indexing are checked against
+    the data: the on-the-fly power count (a kernel without that path would read
+    a table entry that does not exist), the batch and the coefficient rows of a
+    composition tree, the modulus, and the node indices of a composition
+    program.  Per-kind step counts are recomputed."""
+    # a direct-scheme tree with powers beyond the table
+    ex = np.sort(np.random.default_rng(4).choice(100_000, 300, replace=False)).astype(np.int32).reshape(-1, 1)
+    t = fpe.Tree(ex, np.linspace(-1, 1, 300), "direct", fpe.F64)
+    assert t.info.n_offtable > 0
+    blob = t.serialize()
+    assert _hdr_field(blob, _OFF_NOFFT, "<i") == t.info.n_offtable
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree.deserialize(_set_field(blob, _OFF_NOFFT, "<i", 0))
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree.deserialize(_set_field(blob, _OFF_NPAIRS, "<i", t.info.n_pair_ops + 1))
+    back = fpe.Tree.deserialize(blob)
+    assert list(back.info.n_ops_kind) == list(t.info.n_ops_kind)
+    assert back.info.n_offtable == t.info.n_offtable
+    # a batch of 4 rows mod 2^31 - 1 whose batch field claims 10^6
+    rows = np.random.default_rng(5).integers(0, fpe.P31, size=(4, 32)).astype(np.uint64)
+    tc = fpe.Tree(np.arange(32, dtype=np.int32).reshape(-1, 1), rows, "balanced", fpe.MODP, fpe.P31)
+    blob = tc.serialize()
+    assert _hdr_field(blob, _OFF_BATCH, "<q") == 4
+    for bad in (10 ** 6, 0, -3, 5):
+        with pytest.raises(fpe.FpeError):
+            fpe.Tree.deserialize(_set_field(blob, _OFF_BATCH, "<q", bad))
+    # the modulus must be one the kernels implement, and hold every residue
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree.deserialize(_set_field(blob, _OFF_MOD, "<Q", 1000))
+    # an FP64 tree claiming to be a batch composition tree
+    with pytest.raises(fpe.FpeError):
+        fpe.Tree.deserialize(_set_field(t.serialize(), _OFF_DOMAIN, "<i", fpe.MODP))
+    assert fpe.Tree.deserialize(blob).info.batch == 4
