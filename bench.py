@@ -133,7 +133,7 @@ def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, loads=(0.5, 0.8, 0.95))
         out = torch.empty(n, dtype=torch.float64, device=dev)
         prepared.append((r.arrival_s, t, pts, out, m))
     torch.cuda.synchronize()
-    budget = 2 << 30
+    budget = 8 << 30
     # FP32 operations of the compensated walks of one pass over the stream
     step_ops = float(sum(sum(k * o for k, o in zip(t.info.n_ops_kind, DF32_OPS_BY_KIND)) * m.points.shape[1]
                          for _, t, _, _, m in prepared))
@@ -284,7 +284,7 @@ def bigint_phase(fpe, torch, dev, reps: int = 3):
                 e0 = torch.cuda.Event(enable_timing=True)
                 e1 = torch.cuda.Event(enable_timing=True)
                 e0.record()
-                fpe.eval_bigint(t, x, out=out, workspace=ws, lout=lout)
+                fpe.eval_bigint(t, x, out=out, workspace=ws, lout=lout, check=False)
                 e1.record()
                 torch.cuda.synchronize()
                 ms.append(e0.elapsed_time(e1))

@@ -190,7 +190,12 @@ typedef struct {
 /* Workspace needed by fpe_evaluate for npts points (0 unless FPE_F32C). */
 size_t fpe_workspace_bytes(const fpe_tree* t, int64_t npts);
 
-/* Evaluate the uploaded tree at npts points.
+/* Evaluate the uploaded tree at npts points: the coefficient walk of
+ * Section 2.1 (each step one multiplication and one addition, in the fused
+ * form u(P) = c(P) + sum_C u(C) x^{d(C)}), with the distinct powers x^d
+ * precomputed per point by fast exponentiation (Section 2.2, Table 1); the
+ * value is that of the evaluation tree (Section 1, Definition), which every
+ * function scheme makes equal to p(x) in exact arithmetic.
  *   pts  host array of nvars device pointers, each to npts values (SoA):
  *        double for FPE_F64 / FPE_F32C, uint64_t residues < p for FPE_MODP;
  *        for FPE_IVAL each points to double[2 * npts], interval i of that
@@ -225,8 +230,13 @@ fpe_status fpe_evaluate(const fpe_tree* t, const void* const* pts, int64_t npts,
 fpe_status fpe_evaluate_noalloc(const fpe_tree* t, const void* const* pts, int64_t npts, void* out,
                                 const fpe_eval_opts* opts, void* stream);
 
-/* Composition over Z/(2^31 - 1): for every instance r of the batch compiled into t
- * (univariate, FPE_MODP, modulus 2^31 - 1), out[r] = p_r(q_r(x)).
+/* Composition over Z/(2^31 - 1) (the title problem; Section 1.2: the
+ * divide-and-conquer schemes suit elements whose size grows linearly with
+ * each multiplication, such as polynomials): the coefficient walk of
+ * Section 2.1 with polynomial values, the powers q^d by the tree's
+ * multiplication chain (Section 2.2).  For every instance r of the batch
+ * compiled into t (univariate, FPE_MODP, modulus 2^31 - 1),
+ * out[r] = p_r(q_r(x)).
  *   q    device uint32[batch * (dq + 1)], coefficient j of instance r at r*(dq+1)+j, < p
  *   out  device uint32[batch * (deg_p * dq + 1)], coefficients by exponent
  *   workspace  device buffer of fpe_compose_workspace_bytes() bytes */
@@ -250,48 +260,95 @@ int32_t fpe_bigint_out_limbs(const fpe_tree* t, int32_t lx);
 size_t fpe_bigint_workspace_bytes(const fpe_tree* t, int32_t lout, int64_t batch);
 fpe_status fpe_eval_bigint(const fpe_tree* t, const uint32_t* x, int32_t lx, int64_t batch, uint32_t* out,
                            int32_t lout, void* workspace, size_t workspace_bytes, void* stream);
+/* Waits for stream, then reads the overflow flag that the last fpe_eval_bigint
+ * on this workspace wrote (a value needed more than lout limbs, which the
+ * host's lout bound rules out; a device-side check).  FPE_OK, or FPE_ENOMEM
+ * if the result was truncated.  This call synchronises; fpe_eval_bigint does not. */
+fpe_status fpe_bigint_status(const void* workspace, void* stream);
 fpe_status fpe_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out,
                        void* workspace, size_t workspace_bytes, void* stream);
 
 /* ------------------------------------------------------------------------
- * Serving: a persistent request loop with continuous batching.
- * Requests of uneven size are admitted while their bytes fit the HBM budget
- * and a slot is free; admitted requests are packed into one fused launch
- * (a work table of (tree, point range) blocks) replayed through a HIP graph;
- * requests arriving while a batch runs join the next one.  The server keeps
- * uploaded trees resident (by the caller's device image) and records the
- * latency of every request from submit to completion.
+ * Serving: a persistent request loop with continuous batching (the walk of
+ * Section 2.1 run for many requests at once; the trees are compiled once and
+ * stay resident, the "subsequent fast evaluation" of Section 1).
+ *
+ * Requests of uneven size are admitted in arrival order while the bytes they
+ * use fit the HBM budget and an in-flight slot is free.  Admitted FPE_F64 /
+ * FPE_F32C evaluate requests are packed into one fused launch (a work table
+ * of (tree, point range) blocks) replayed through a HIP graph; FPE_MODP
+ * evaluate and compose requests of the batch run beside it as their own
+ * launches.  Each batch runs on one of two streams of the server (default
+ * priority), so a batch overlaps the tail of the one before it; requests
+ * arriving while batches run join the next one.  Each point's result depends
+ * only on its own walk, so a request's output is the same bits alone
+ * (fpe_evaluate / fpe_compose) and in any mix.  Latency is measured from
+ * submit to the host observing completion.
+ *
+ * Device memory: the server takes one caller-owned device buffer (for
+ * example a torch uint8 tensor) of fpe_server_workspace_bytes(hbm_budget)
+ * bytes for its work tables and the per-request scratch (fallback lists,
+ * composition workspaces), and allocates no device memory itself.
+ * Ordering: before each batch the server's streams wait for the work the
+ * caller enqueued on `stream` (given at creation) up to that moment, so
+ * inputs written there before submit are seen; outputs are complete once
+ * poll reports the ticket done or wait returns.
  * ---------------------------------------------------------------------- */
 typedef struct fpe_server fpe_server;
 
+typedef enum { FPE_REQ_EVALUATE = 0, FPE_REQ_COMPOSE = 1 } fpe_request_kind;
+
 typedef struct {
-  const fpe_tree* tree;     /* compiled for FPE_F64 or FPE_F32C and uploaded */
-  const double* pts[8];     /* nvars device pointers (SoA) */
-  int64_t npts;
-  double* out;              /* device double[npts] */
-  float* cond_out;          /* optional device float[npts] */
+  const fpe_tree* tree;     /* uploaded; FPE_F64, FPE_F32C or FPE_MODP (2^61 - 1) for evaluate,
+                               FPE_MODP 2^31 - 1 (a batch of p) for compose */
+  const void* pts[8];       /* evaluate: nvars device pointers (SoA), double or uint64 residues */
+  int64_t npts;             /* evaluate: points */
+  void* out;                /* evaluate: device double[npts] / uint64[npts];
+                               compose: device uint32[batch * (deg_p * dq + 1)] */
+  float* cond_out;          /* optional device float[npts] (FPE_F32C) */
   double tol;               /* FPE_F32C tolerance (<= 0: 1e-12) */
-  int32_t domain;           /* FPE_F64 or FPE_F32C */
+  int32_t domain;           /* the tree's domain */
+  int32_t kind;             /* fpe_request_kind */
+  const uint32_t* q;        /* compose: device uint32[batch * (dq + 1)] */
+  int32_t dq;               /* compose: degree of q (>= 1) */
 } fpe_request;
 
 typedef struct {
   int64_t submitted, completed, rejected;
   int64_t batches;
-  double p50_ms, p99_ms, mean_ms;   /* submit -> completion latency */
-  double term_evals;                /* sum of nonzero terms x points over completed requests */
-  double busy_s;                    /* wall time with work on the GPU */
+  double p50_ms, p99_ms, mean_ms;   /* submit -> completion latency (quantiles within 0.5 %) */
+  double term_evals;                /* sum of nonzero terms x points over completed evaluate requests */
+  double busy_s;                    /* wall time with at least one batch on the GPU */
   double fallback_frac;             /* re-evaluated points / points (FPE_F32C requests) */
-  int64_t hbm_in_use;               /* workspace bytes held by admitted requests */
+  int64_t hbm_in_use;               /* bytes counted against the budget by admitted requests */
+  int64_t compose_instances;        /* instances of completed compose requests */
 } fpe_stats;
 
-/* hbm_budget: bytes of device workspace the server may hold at once (it
- * allocates them once, here); max_inflight: requests admitted at once. */
-fpe_status fpe_server_create(size_t hbm_budget, int32_t max_inflight, void* stream, fpe_server** out);
-fpe_status fpe_server_submit(fpe_server* s, const fpe_request* r, uint64_t* ticket);  /* non-blocking */
+/* Device bytes the server needs for a given budget: its work tables and the
+ * pool that per-request scratch comes from. */
+size_t fpe_server_workspace_bytes(size_t hbm_budget);
+
+/* workspace: caller-owned device buffer of fpe_server_workspace_bytes(hbm_budget)
+ *   bytes, 256-byte aligned, which must outlive the server.
+ * hbm_budget: bytes admitted requests may use at once.  A request counts its
+ *   points (8 B per variable and point), output, condition output, fallback
+ *   list (4 B per point, FPE_F32C), composition workspace and tree image.
+ * max_inflight: requests admitted at once (at most 256).
+ * stream: the caller's stream whose prior work every batch waits for (NULL =
+ *   the default stream).
+ * Errors: FPE_EINVAL, FPE_ENOMEM (workspace too small), FPE_EDEVICE. */
+fpe_status fpe_server_create(void* workspace, size_t workspace_bytes, size_t hbm_budget, int32_t max_inflight,
+                             void* stream, fpe_server** out);
+/* Non-blocking.  FPE_EBUDGET if the request alone exceeds the budget. */
+fpe_status fpe_server_submit(fpe_server* s, const fpe_request* r, uint64_t* ticket);
+/* *done = 1 once the request has completed (its outputs are written);
+ * completed requests keep no state, so any earlier ticket no longer pending
+ * reports done.  FPE_EINVAL for a ticket never issued. */
 fpe_status fpe_server_poll(fpe_server* s, uint64_t ticket, int32_t* done);
 fpe_status fpe_server_wait(fpe_server* s, uint64_t ticket);
 fpe_status fpe_server_drain(fpe_server* s);
 fpe_status fpe_server_stats(fpe_server* s, fpe_stats* st);
+/* Drains, then releases the server (not the caller's workspace). */
 void fpe_server_destroy(fpe_server* s);
 
 #ifdef __cplusplus

@@ -62,10 +62,14 @@ class EvalOpts(ctypes.Structure):
                 ("bound_out", ctypes.c_void_p)]
 
 
+REQ_EVALUATE, REQ_COMPOSE = 0, 1
+
+
 class Request(ctypes.Structure):
     _fields_ = [("tree", ctypes.c_void_p), ("pts", ctypes.c_void_p * 8), ("npts", ctypes.c_int64),
                 ("out", ctypes.c_void_p), ("cond_out", ctypes.c_void_p), ("tol", ctypes.c_double),
-                ("domain", ctypes.c_int32)]
+                ("domain", ctypes.c_int32), ("kind", ctypes.c_int32), ("q", ctypes.c_void_p),
+                ("dq", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -73,7 +77,8 @@ class Stats(ctypes.Structure):
                 ("rejected", ctypes.c_int64), ("batches", ctypes.c_int64),
                 ("p50_ms", ctypes.c_double), ("p99_ms", ctypes.c_double), ("mean_ms", ctypes.c_double),
                 ("term_evals", ctypes.c_double), ("busy_s", ctypes.c_double),
-                ("fallback_frac", ctypes.c_double), ("hbm_in_use", ctypes.c_int64)]
+                ("fallback_frac", ctypes.c_double), ("hbm_in_use", ctypes.c_int64),
+                ("compose_instances", ctypes.c_int64)]
 
 
 def _load():
@@ -105,7 +110,8 @@ def _load():
         "fpe_evaluate_noalloc": ([P, P, i64, P, ctypes.POINTER(EvalOpts), P], i32),
         "fpe_compose_workspace_bytes": ([P, i32], sz),
         "fpe_compose": ([P, P, i32, P, P, sz, P], i32),
-        "fpe_server_create": ([sz, i32, P, ctypes.POINTER(P)], i32),
+        "fpe_server_workspace_bytes": ([sz], sz),
+        "fpe_server_create": ([P, sz, sz, i32, P, ctypes.POINTER(P)], i32),
         "fpe_server_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(u64)], i32),
         "fpe_server_poll": ([P, u64, ctypes.POINTER(i32)], i32),
         "fpe_server_wait": ([P, u64], i32),
@@ -115,6 +121,7 @@ def _load():
         "fpe_bigint_out_limbs": ([P, i32], i32),
         "fpe_bigint_workspace_bytes": ([P, i32, i64], sz),
         "fpe_eval_bigint": ([P, P, i32, i64, P, i32, P, sz, P], i32),
+        "fpe_bigint_status": ([P, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -129,9 +136,11 @@ EXPORTED = ["fpe_last_error", "fpe_version", "fpe_compile", "fpe_tree_free", "fp
             "fpe_tree_get_info", "fpe_tree_node_exps", "fpe_tree_device_bytes", "fpe_tree_upload",
             "fpe_tree_serialize", "fpe_tree_deserialize", "fpe_workspace_bytes", "fpe_evaluate",
             "fpe_evaluate_noalloc",
-            "fpe_compose_workspace_bytes", "fpe_compose", "fpe_server_create", "fpe_server_submit",
+            "fpe_compose_workspace_bytes", "fpe_compose", "fpe_server_workspace_bytes", "fpe_server_create",
+            "fpe_server_submit",
             "fpe_server_poll", "fpe_server_wait", "fpe_server_drain", "fpe_server_stats",
-            "fpe_server_destroy", "fpe_bigint_out_limbs", "fpe_bigint_workspace_bytes", "fpe_eval_bigint"]
+            "fpe_server_destroy", "fpe_bigint_out_limbs", "fpe_bigint_workspace_bytes", "fpe_eval_bigint",
+            "fpe_bigint_status"]
 
 
 def _check(st: int):
@@ -337,10 +346,12 @@ def evaluate_noalloc(tree: Tree, pts, out, tol: float = 1e-12, force: int = 0, c
     return out
 
 
-def eval_bigint(tree: Tree, x, lout=None, out=None, workspace=None, stream=None):
+def eval_bigint(tree: Tree, x, lout=None, out=None, workspace=None, stream=None, check=True):
     """p(x_r) over the natural numbers for every point r: ``x`` is a device
     int32 tensor [batch, lx] of 16-bit limbs (least significant first); the
-    result is [batch, lout] int32 limbs (values < 2^16)."""
+    result is [batch, lout] int32 limbs (values < 2^16).  With ``check`` the
+    device overflow flag is read back (fpe_bigint_status, which waits for the
+    stream) and a truncated result raises."""
     import torch
     if tree._dev is None:
         raise FpeError(-1, "tree is not uploaded")
@@ -360,6 +371,8 @@ def eval_bigint(tree: Tree, x, lout=None, out=None, workspace=None, stream=None)
     _check(lib.fpe_eval_bigint(tree.handle, ctypes.c_void_p(x.data_ptr()), lx, batch,
                                ctypes.c_void_p(out.data_ptr()), lout, ctypes.c_void_p(workspace.data_ptr() + off),
                                workspace.numel() - off, _stream_ptr(stream)))
+    if check:
+        _check(lib.fpe_bigint_status(ctypes.c_void_p(workspace.data_ptr() + off), _stream_ptr(stream)))
     return out
 
 
@@ -385,27 +398,58 @@ def compose(tree: Tree, q, out=None, workspace=None, stream=None):
 
 
 class Server:
-    """Continuous-batching request loop (fpe_server_*)."""
+    """Continuous-batching request loop (fpe_server_*).  Its device workspace
+    (work tables and per-request scratch) is a torch tensor owned here."""
 
-    def __init__(self, hbm_budget: int, max_inflight: int = 64, stream=None):
+    def __init__(self, hbm_budget: int, max_inflight: int = 64, stream=None, device="cuda"):
+        import torch
+        nb = int(lib.fpe_server_workspace_bytes(hbm_budget))
+        self._ws = torch.empty(nb + 256, dtype=torch.uint8, device=device)
+        off = (-self._ws.data_ptr()) % 256
         h = ctypes.c_void_p()
-        _check(lib.fpe_server_create(hbm_budget, max_inflight, _stream_ptr(stream), ctypes.byref(h)))
+        _check(lib.fpe_server_create(ctypes.c_void_p(self._ws.data_ptr() + off), nb, hbm_budget, max_inflight,
+                                     _stream_ptr(stream), ctypes.byref(h)))
         self._h = h
 
     def submit(self, tree: Tree, pts, out, domain=F32C, tol=1e-12, cond_out=None) -> int:
+        """An evaluate request: FPE_F64 / FPE_F32C (float64 points and output)
+        or FPE_MODP (residues as int64 tensors)."""
         n = pts[0].numel()
-        if len(pts) != tree.nvars or any(p.numel() != n or not p.is_contiguous() for p in pts) \
-                or out.numel() < n or (cond_out is not None and cond_out.numel() < n):
-            raise FpeError(-1, "one contiguous point array per variable, all of one length, and outputs that long")
+        if len(pts) != tree.nvars or any(p.numel() != n or not p.is_contiguous() or p.element_size() != 8
+                                         for p in pts) \
+                or out.numel() < n or not out.is_contiguous() or out.element_size() != 8 \
+                or (cond_out is not None and (cond_out.numel() < n or cond_out.element_size() != 4)):
+            raise FpeError(-1, "one contiguous 8-byte point array per variable, all of one length, and outputs that long")
         r = Request()
         r.tree = tree.handle
         for j, p in enumerate(pts):
             r.pts[j] = p.data_ptr()
-        r.npts = pts[0].numel()
+        r.npts = n
         r.out = out.data_ptr()
         r.cond_out = cond_out.data_ptr() if cond_out is not None else None
         r.tol = tol
         r.domain = domain
+        r.kind = REQ_EVALUATE
+        t = ctypes.c_uint64()
+        _check(lib.fpe_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
+        return t.value
+
+    def submit_compose(self, tree: Tree, q, out) -> int:
+        """A compose request: p_r(q_r(x)) mod 2^31 - 1 for every instance of
+        ``tree``; ``q`` is int32 [batch, dq + 1], ``out`` int32
+        [batch, deg_p * dq + 1]."""
+        batch, dq1 = q.shape
+        dp = int(tree.node_exps().max())
+        if batch != tree.batch or not q.is_contiguous() or q.element_size() != 4 or not out.is_contiguous() \
+                or out.element_size() != 4 or out.numel() < batch * (dp * (dq1 - 1) + 1):
+            raise FpeError(-1, "q must be [batch, dq + 1] and out [batch, deg_p * dq + 1], contiguous 32-bit")
+        r = Request()
+        r.tree = tree.handle
+        r.out = out.data_ptr()
+        r.domain = tree.domain
+        r.kind = REQ_COMPOSE
+        r.q = q.data_ptr()
+        r.dq = dq1 - 1
         t = ctypes.c_uint64()
         _check(lib.fpe_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
         return t.value
@@ -430,6 +474,7 @@ class Server:
         if getattr(self, "_h", None) and lib is not None:
             lib.fpe_server_destroy(self._h)
             self._h = None
+        self._ws = None      # the workspace outlives the server
 
     def __del__(self):
         self.close()

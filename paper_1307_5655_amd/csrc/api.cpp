@@ -26,6 +26,10 @@ void layout(fpe_tree* t) {
   // the FP64 sum of n non-negative terms is within n 2^-53 of the exact one
   c1 *= 1.0 + (double)(t->nodes.size() + 1) * std::ldexp(1.0, -52);
   t->abs_scale = df32_abs_scale((int64_t)t->ops64.size(), c1);
+  // the composition rows as the kernel reads them (32-bit residues), kept by
+  // the tree so that the upload is an asynchronous copy from live memory
+  t->coef_rows32.clear();
+  if (t->domain == FPE_MODP && t->modulus == kP31) t->coef_rows32.assign(t->coef_rows.begin(), t->coef_rows.end());
   size_t off = 0;
   // each op array is followed by kOpTail zero records (the walk reads ahead)
   t->off_ops64 = off;
@@ -149,11 +153,9 @@ fpe_status fpe_tree_upload(fpe_tree* t, void* dev_buf, size_t bytes, void* strea
   if (e == hipSuccess && !t->chain.empty())
     e = hipMemcpyAsync(b + t->off_chain, t->chain.data(), t->chain.size() * sizeof(ChainStep),
                        hipMemcpyHostToDevice, st);
-  if (e == hipSuccess && t->domain == FPE_MODP && t->modulus == kP31) {
-    std::vector<uint32_t>* rows = new std::vector<uint32_t>(t->coef_rows.begin(), t->coef_rows.end());
-    e = hipMemcpy(b + t->off_coef, rows->data(), rows->size() * sizeof(uint32_t), hipMemcpyHostToDevice);
-    delete rows;
-  }
+  if (e == hipSuccess && t->domain == FPE_MODP && t->modulus == kP31)
+    e = hipMemcpyAsync(b + t->off_coef, t->coef_rows32.data(), t->coef_rows32.size() * sizeof(uint32_t),
+                       hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
   t->dev = dev_buf;
   return FPE_OK;
@@ -376,6 +378,16 @@ fpe_status fpe_eval_bigint(const fpe_tree* t, const uint32_t* x, int32_t lx, int
   if (lout > kBigMaxLimbs) return fail(FPE_EUNSUPPORTED, "more output limbs than the kernel's columns hold");
   if (lout < bigint_limbs_needed(t, lx)) return fail(FPE_EINVAL, "lout smaller than fpe_bigint_out_limbs()");
   return launch_bigint(t, x, lx, batch, out, lout, workspace, workspace_bytes, stream);
+}
+
+fpe_status fpe_bigint_status(const void* workspace, void* stream) {
+  if (!workspace) return fail(FPE_EINVAL, "NULL workspace");
+  int32_t flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, workspace, sizeof flag, hipMemcpyDeviceToHost, (hipStream_t)stream);
+  if (e == hipSuccess) e = hipStreamSynchronize((hipStream_t)stream);
+  if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("bigint status: ") + hipGetErrorString(e));
+  if (flag) return fail(FPE_ENOMEM, "a big-integer value needed more than lout limbs (result truncated)");
+  return FPE_OK;
 }
 
 fpe_status fpe_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* workspace,

@@ -179,6 +179,7 @@ struct fpe_tree {
   std::vector<fpe_node> nodes;
   std::vector<int32_t> exps;            // n_nodes x nvars
   std::vector<uint64_t> coef_rows;      // batch x n_nodes (mod p), node order
+  std::vector<uint32_t> coef_rows32;    // the same as 32-bit residues (composition mod 2^31 - 1)
   // program
   std::vector<fpe::OpF64> ops64;
   std::vector<fpe::OpF32> ops32;

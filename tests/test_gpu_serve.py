@@ -75,12 +75,20 @@ def test_serve_alone_vs_mix_bit_identical(dev):
     srv.close()
 
 
+def request_bytes(t, npts, dom, cond=False):
+    """The bytes a served evaluate request counts against the budget (as the
+    header states: points, output, condition output, fallback list, tree
+    image)."""
+    scratch = ((4 * npts + 255) // 256) * 256 if dom == fpe.F32C else 0
+    return t.device_bytes() + scratch + npts * (8 * t.nvars + 8 + (4 if cond else 0))
+
+
 def test_serve_tight_budget_admission_and_rejection(dev):
     say("serve: budget admission and rejection")
     reqs = prepare(make_requests(24, 2, max_terms=400, max_pts=20_000), dev)
-    biggest = max(p[0].numel() for _, _, p, _ in reqs)
-    # the budget holds the fallback list of about one large request at a time
-    srv = fpe.Server(hbm_budget=(biggest * 4 + 256) * 1, max_inflight=8)
+    biggest = max(request_bytes(t, p[0].numel(), dom) for t, dom, p, _ in reqs)
+    # the budget holds about one large request at a time
+    srv = fpe.Server(hbm_budget=biggest, max_inflight=8)
     outs, tickets = [], []
     for t, dom, pts, m in reqs:
         o = torch.empty(pts[0].numel(), dtype=torch.float64, device=dev)
@@ -92,15 +100,85 @@ def test_serve_tight_budget_admission_and_rejection(dev):
         assert np.array_equal(o.cpu().numpy(), fpe.evaluate(t, pts).cpu().numpy())
     st = srv.stats()
     assert st.completed == len(reqs) and st.hbm_in_use == 0
-    # a request whose workspace can never fit is rejected with FPE_EBUDGET
+    assert st.batches >= 4          # the budget split the stream into several batches
+    # a request that can never fit is rejected with FPE_EBUDGET
     g = np.random.default_rng(3)
-    m = fpe_inputs.random_multi_f64(1, 20, biggest * 2, g)
+    n = biggest // 16 + 1
+    m = fpe_inputs.random_multi_f64(1, 20, n, g)
     t = fpe.Tree(m.exps, m.coeffs, "horner", fpe.F32C).upload(dev)
+    assert request_bytes(t, n, fpe.F32C) > biggest
     pts = [torch.from_numpy(m.points[0]).to(dev)]
     with pytest.raises(fpe.FpeError) as e:
-        srv.submit(t, pts, torch.empty(biggest * 2, dtype=torch.float64, device=dev), domain=fpe.F32C)
+        srv.submit(t, pts, torch.empty(n, dtype=torch.float64, device=dev), domain=fpe.F32C)
     assert e.value.status == -4
     assert srv.stats().rejected == 1
+    # tickets: completed ones keep no state and report done; a ticket never
+    # issued is an error
+    assert all(srv.poll(tk) for tk in tickets)
+    with pytest.raises(fpe.FpeError):
+        srv.poll(max(tickets) + 1000)
+    srv.close()
+
+
+def test_serve_modp_and_compose_requests_in_the_mix(dev):
+    """Exact requests join the batches: mod 2^61 - 1 evaluations and batched
+    compositions mod 2^31 - 1, beside compensated and FP64 evaluations; each
+    result is the same as the request alone."""
+    say("serve: mod-p evaluate and compose requests in the mix")
+    from oracle import native
+    fl = prepare(make_requests(12, 7, max_terms=800, max_pts=30_000), dev)
+    mods = []
+    for k in range(4):
+        v = 1 + k % 3
+        m = fpe_inputs.random_modp_poly(v, 300 + 100 * k, {1: 700, 2: 40, 3: 18}[v], 5000 + 77 * k, seed=(910, k))
+        t = fpe.Tree(m.exps, m.coeffs, ["horner", "estrin", "balanced"][k % 3], fpe.MODP, fpe.P61).upload(dev)
+        px = [torch.from_numpy(np.ascontiguousarray(m.points[j]).view(np.int64)).to(dev)
+              for j in range(m.points.shape[0])]
+        mods.append((t, px, m))
+    comps = []
+    g = np.random.default_rng([13075655, 920])
+    for k, (b, dp, dq) in enumerate([(64, 63, 7), (16, 255, 15), (33, 40, 3)]):
+        P = g.integers(0, fpe.P31, size=(b, dp + 1)).astype(np.uint64)
+        Q = g.integers(0, fpe.P31, size=(b, dq + 1)).astype(np.int32)
+        t = fpe.Tree(np.arange(dp + 1, dtype=np.int32).reshape(-1, 1), P, ["balanced", "horner", "estrin"][k],
+                     fpe.MODP, fpe.P31).upload(dev)
+        comps.append((t, torch.from_numpy(Q).to(dev), P, Q))
+    torch.cuda.synchronize()
+    srv = fpe.Server(hbm_budget=512 << 20, max_inflight=32)
+    outs = []
+    for i in range(max(len(fl), len(mods), len(comps))):
+        if i < len(fl):
+            t, dom, pts, m = fl[i]
+            o = torch.full((pts[0].numel(),), np.nan, dtype=torch.float64, device=dev)
+            outs.append(("f", i, o, srv.submit(t, pts, o, domain=dom)))
+        if i < len(mods):
+            t, px, m = mods[i]
+            o = torch.full((px[0].numel(),), -1, dtype=torch.int64, device=dev)
+            outs.append(("m", i, o, srv.submit(t, px, o, domain=fpe.MODP)))
+        if i < len(comps):
+            t, q, P, Q = comps[i]
+            o = torch.full((P.shape[0], (P.shape[1] - 1) * (Q.shape[1] - 1) + 1), -1, dtype=torch.int32, device=dev)
+            outs.append(("c", i, o, srv.submit_compose(t, q, o)))
+    srv.drain()
+    for kind, i, o, tk in outs:
+        assert srv.poll(tk)
+        got = o.cpu().numpy()
+        if kind == "f":
+            t, dom, pts, m = fl[i]
+            assert np.array_equal(got, fpe.evaluate(t, pts).cpu().numpy()), i
+        elif kind == "m":
+            t, px, m = mods[i]
+            assert np.array_equal(got, fpe.evaluate(t, px).cpu().numpy()), i
+            assert np.array_equal(got.view(np.uint64), native.modp_eval(m.exps, m.coeffs, fpe.P61, m.points)), i
+        else:
+            t, q, P, Q = comps[i]
+            assert np.array_equal(got, fpe.compose(t, q).cpu().numpy()), i
+            want = native.compose_modp(P.astype(np.uint32), Q.astype(np.uint32), fpe.P31)
+            assert np.array_equal(got.view(np.uint32), want), i
+    st = srv.stats()
+    assert st.completed == st.submitted == len(outs)
+    assert st.compose_instances == sum(P.shape[0] for _, _, P, _ in comps)
+    assert st.hbm_in_use == 0
     srv.close()
 
 
