@@ -4,20 +4,26 @@ Timed step: the sparse univariate workload of degrees 3000 and 5000
 (coefficients U[-1, 1], 10 % of the exponents below the degree zeroed),
 1e7 points U[-1.05, 1.05] resident in HBM, each degree under the balanced,
 Estrin and Hörner schemes, each in the served form (compensated FP32 with a
-running error bound and FP64 re-evaluation of flagged points) and in plain
-FP64: 12 evaluations, 8.1e11 term-evaluations per step.  Trees are compiled
-and uploaded once, before the timed region.
+running error bound, each point's condition number written beside its value,
+and FP64 re-evaluation of flagged points) and in plain FP64: 12 evaluations,
+4.3e11 term-evaluations per step.  Trees are compiled and uploaded once,
+before the timed region.
 
-After the timed region (not part of ``value``): the accuracy of the last step
-against the CPU oracle on a sample; a served stream (Poisson arrivals of
-uneven evaluate requests through the continuous-batching server: 10^4
-requests, first all at once for the saturation rate, then at 0.5, 0.8 and 0.95
-times that rate) for p50/p99 latency; the exact mod 2^61-1 trivariate workload and the batched
-composition mod 2^31-1, each timed beside the main line; and the CPU oracle
-timed on a bounded sample of the step's workload.
+After the timed region (not part of ``value``): the compensated walks without
+condition output; the accuracy of a step against the CPU oracle on a sample;
+the measured issue rates of the operations the kernels are bound by (rate
+probes) and the HBM copy bandwidth; the dense degree-1023 polynomial at 1e5
+points; a served stream (Poisson arrivals of uneven evaluate requests through
+the continuous-batching server: 10^4 requests, first all at once for the
+saturation rate, then at 0.5, 0.8 and 0.95 times that rate) for p50/p99
+latency; the exact mod 2^61-1 trivariate workload and the batched composition
+mod 2^31-1, each with its roofline; intervals; big integers; and the CPU
+oracle timed on bounded samples (plain FP64 Hörner on 1 core and on all
+cores, the mod-p definition, schoolbook composition).
 
 Prints one JSON line; ``roofline`` describes the dominant kernel (the
-compensated-FP32 walk), ``roofline_f64`` the plain FP64 walk.
+compensated-FP32 walk, priced on 11 FP32 operations per term-evaluation),
+``roofline_f64`` the plain FP64 walk.
 """
 from __future__ import annotations
 
@@ -50,6 +56,12 @@ FP64_FMA_PEAK = 256 * 64 * 2.4e9
 # condition numbers of the workload are reported from the oracle's sample
 # instead).
 DF32_OPS_BY_KIND = (17, 17, 16, 18, 0)
+# The algorithmic FP32 operation count of one compensated step that the
+# roofline fraction is quoted on: TwoProd 2, TwoSum 6, first-order error
+# propagation 2, running bound 1 (a compensated Hörner step).  The walk's own
+# count (above) adds the double-float renormalisation and cross terms that
+# keep 48 bits over a chain of 5000 steps; its fraction is reported beside.
+DF32_ALG_OPS = 11
 
 
 def log(msg):
@@ -140,10 +152,13 @@ def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, loads=(0.5, 0.8, 0.95))
     # each request's ideal time on the roofline: the larger of its compensated
     # walk's FP32 operations at the VALU peak and its point and result bytes
     # (8 v + 8 per point) at the HBM peak
-    ideal_s = float(sum(max(sum(k * o for k, o in zip(t.info.n_ops_kind, DF32_OPS_BY_KIND)) * m.points.shape[1]
-                            / FP32_VALU_PEAK,
+    ideal_s = float(sum(max(DF32_ALG_OPS * t.info.n_terms * m.points.shape[1] / FP32_VALU_PEAK,
                             (8 * m.points.shape[0] + 8) * m.points.shape[1] / (HBM_PEAK_GBS * 1e9))
                         for _, t, _, _, m in prepared))
+    ideal_impl_s = float(sum(max(sum(k * o for k, o in zip(t.info.n_ops_kind, DF32_OPS_BY_KIND)) * m.points.shape[1]
+                                 / FP32_VALU_PEAK,
+                                 (8 * m.points.shape[0] + 8) * m.points.shape[1] / (HBM_PEAK_GBS * 1e9))
+                             for _, t, _, _, m in prepared))
 
     srv = fpe.Server(hbm_budget=budget, max_inflight=64)
     t0 = time.perf_counter()
@@ -156,7 +171,8 @@ def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, loads=(0.5, 0.8, 0.95))
            "term_evals_per_s": st.term_evals / wall_sat, "batches": st.batches,
            "fallback_frac": st.fallback_frac, "df32_step_ops": step_ops,
            "fp32_peak_frac_of_wall": step_ops / (wall_sat * FP32_VALU_PEAK),
-           "ideal_s": ideal_s, "roofline_frac_of_wall": ideal_s / wall_sat}
+           "ideal_s": ideal_s, "roofline_frac_of_wall": ideal_s / wall_sat,
+           "ideal_s_walk_ops": ideal_impl_s, "roofline_frac_of_wall_walk_ops": ideal_impl_s / wall_sat}
     srv.close()
     sat_rps = nreq / wall_sat
 
@@ -199,6 +215,178 @@ def served_phase(fpe, fpe_inputs, torch, dev, nreq: int, loads=(0.5, 0.8, 0.95))
     return sat, lat
 
 
+# Published MI355X peaks the probes are compared with (per second).
+PUBLISHED = {"fma_f64": FP64_FMA_PEAK, "fma_f32": FP32_VALU_PEAK, "mfma_i8": 5.0e15, "copy": HBM_PEAK_GBS * 1e9,
+             "mad_u64": FP64_FMA_PEAK}
+
+
+def probe_phase(torch, dev):
+    """Measured issue rates of the operations the kernels are bound by
+    (libfpe_probe.so: independent chains of one operation per thread), and the
+    HBM bandwidth of a plain copy."""
+    import ctypes
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_1307_5655_amd", "libfpe_probe.so"))
+    L.fpe_probe_launch.argtypes = [ctypes.c_int32, ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p]
+    L.fpe_probe_launch.restype = ctypes.c_double
+    st = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    blocks = 256 * 16
+    sink = torch.empty(blocks * 256 * 16, dtype=torch.uint8, device=dev)
+    nbytes = 2 << 30
+    src = torch.ones(nbytes // 8, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    runs = [("fma_f64", 0, blocks, 10000, "FP64 FMA/s"), ("fma_f32", 1, blocks, 10000, "FP32 FMA/s (not packed)"),
+            ("df32_step", 2, blocks, 4000, "compensated steps/s"), ("m61_mac", 3, blocks, 4000, "mod 2^61-1 MAC/s"),
+            ("mad_u64", 4, blocks, 10000, "v_mad_u64_u32/s"), ("mfma_i8", 5, 256 * 8, 100, "int8 MFMA ops/s"),
+            ("copy", 6, 256 * 32, 0, "bytes/s read + written")]
+    res = {}
+    for name, kind, b, iters, unit in runs:
+        args = (kind, b, iters, ctypes.c_void_p(sink.data_ptr()), ctypes.c_void_p(src.data_ptr()),
+                ctypes.c_void_p(dst.data_ptr()), nbytes, st)
+        if L.fpe_probe_launch(*args) < 0:
+            raise RuntimeError(f"probe {name} failed")
+        ms = []
+        for _ in range(3):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ops = L.fpe_probe_launch(*args)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        m = float(np.median(ms))
+        rate = ops / (m * 1e-3)
+        res[name] = {"rate": rate, "unit": unit, "ms": m}
+        if name in PUBLISHED:
+            res[name]["published_peak"] = PUBLISHED[name]
+            res[name]["frac_of_published"] = rate / PUBLISHED[name]
+    res["df32_step"]["fp32_ops_per_s"] = res["df32_step"]["rate"] * DF32_OPS_BY_KIND[3]
+    del src, dst, sink
+    return res
+
+
+def dense_phase(fpe, fpe_inputs, torch, dev, reps: int = 50):
+    """The plain method at its small size: one dense polynomial of degree 1023
+    at 1e5 points, Hörner and Estrin, plain FP64 (and the compensated form
+    beside it); each figure the average of back-to-back launches."""
+    inp = fpe_inputs.dense_uni()
+    e, c = inp.terms()
+    x = torch.from_numpy(inp.points).to(dev)
+    npts = len(inp.points)
+    res = {}
+    for s in ("horner", "estrin"):
+        for fname, dom in (("f64", fpe.F64), ("f32c", fpe.F32C)):
+            t = fpe.Tree(e, c, s, dom).upload(dev)
+            out = torch.empty(npts, dtype=torch.float64, device=dev)
+            ws = torch.empty(fpe.workspace_bytes(t, npts) + 256, dtype=torch.uint8, device=dev) \
+                if dom == fpe.F32C else None
+            for _ in range(3):
+                fpe.evaluate(t, [x], out=out, workspace=ws)
+            torch.cuda.synchronize()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                fpe.evaluate(t, [x], out=out, workspace=ws)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1) / reps
+            te = float(t.info.n_terms) * npts
+            row = {"ms_per_launch": ms, "term_evals_per_s": te / (ms * 1e-3)}
+            if dom == fpe.F64:
+                row["frac_of_fp64_fma_peak"] = te / (ms * 1e-3) / FP64_FMA_PEAK
+            res[f"{s}_{fname}"] = row
+    return res
+
+
+def compose_macs(tree, dq: int) -> float:
+    """Modular multiply-adds of one instance's composition walk: every child
+    value u(C) times q^{d(C)} (a polynomial product, (deg u(C) + 1) x
+    (d(C) dq + 1) multiply-adds), the root's own power, and the powers q^d
+    built by halving (q^d = q^{floor(d/2)} q^{ceil(d/2)}), as the compiler
+    plans them for composition trees."""
+    nd = tree.nodes()
+    deg = [0] * len(nd)
+    macs = 0.0
+    pdegs = set()
+    for i, n in enumerate(nd):
+        d = int(n["pdeg"])
+        if n["parent"] >= 0:
+            macs += (deg[i] + 1) * (d * dq + 1)
+            par = int(n["parent"])
+            deg[par] = max(deg[par], deg[i] + d * dq)
+        elif d > 0:
+            macs += (deg[i] + 1) * (d * dq + 1)
+        if d > 0:
+            pdegs.add(d)
+    have = {1}
+
+    def ensure(d):
+        nonlocal macs
+        if d in have:
+            return
+        a, b = d // 2, d - d // 2
+        ensure(a)
+        ensure(b)
+        macs += (a * dq + 1) * (b * dq + 1)
+        have.add(d)
+
+    for d in sorted(pdegs):
+        ensure(d)
+    return macs
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_phase(native, fpe_inputs, inputs, degrees, npts_all: int, npts_one: int):
+    """The oracle as it stands on the host cores: plain FP64 Hörner (C,
+    -O2, no fused multiply-add) on 1 core and on all cores, the naive
+    mod 2^61-1 definition on the trivariate workload, and schoolbook
+    composition."""
+    ncores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    model = cpu_model()
+    out = {"model": model}
+    for label, threads, npts in (("all_cores", ncores, npts_all), ("one_core", 1, npts_one)):
+        native.set_threads(threads)
+        te = 0.0
+        c0 = time.perf_counter()
+        for n in degrees:
+            xs_c = np.ascontiguousarray(inputs[n].points[:npts])
+            native.horner_f64(inputs[n].coeffs, xs_c, use_fma=False)
+            te += float(np.count_nonzero(inputs[n].coeffs)) * len(xs_c)
+        c1 = time.perf_counter()
+        out[label] = {"value": te / (c1 - c0), "unit": "term-evals/s", "cores": native.threads(), "kind": "oracle",
+                      "sample": f"plain FP64 Hörner (C, -O2, no fma) over the dense coefficient vectors of "
+                                f"degrees {' and '.join(map(str, degrees))} at their first {npts} points "
+                                f"({te:.3g} term-evals, {c1 - c0:.2f} s), {model}"}
+    native.set_threads(ncores)
+    tri = fpe_inputs.trivariate(npts=20_000)
+    c0 = time.perf_counter()
+    native.modp_eval(tri.exps, tri.coeffs, (1 << 61) - 1, tri.points)
+    c1 = time.perf_counter()
+    te = float(len(tri.coeffs)) * tri.points.shape[1]
+    out["modp_trivariate"] = {"value": te / (c1 - c0), "unit": "term-evals/s", "cores": native.threads(),
+                              "kind": "oracle", "sample": f"naive mod 2^61-1 definition (unsigned __int128), "
+                                                          f"12,341 terms at the first 20,000 points ({c1 - c0:.2f} s)"}
+    cb = fpe_inputs.compose_batch()
+    k = 128
+    c0 = time.perf_counter()
+    native.compose_modp(cb.p[:k], cb.q[:k], (1 << 31) - 1)
+    c1 = time.perf_counter()
+    out["compose"] = {"value": k / (c1 - c0), "unit": "instances/s", "cores": native.threads(), "kind": "oracle",
+                      "sample": f"schoolbook Hörner composition of the first {k} of the 4096 instances "
+                                f"({c1 - c0:.2f} s)"}
+    return out
+
+
 def modp_phase(fpe, fpe_inputs, torch, dev, hev, reps: int = 3):
     """Exact trivariate evaluation mod 2^61-1 (12,341 terms, 1e6 points)."""
     inp = fpe_inputs.trivariate()
@@ -217,6 +405,21 @@ def modp_phase(fpe, fpe_inputs, torch, dev, hev, reps: int = 3):
         m = float(np.median(ms))
         res[s] = {"walk_ms": m, "term_evals_per_s": len(inp.coeffs) * inp.points.shape[1] / (m * 1e-3)}
     return res
+
+
+def modp_roofline(modp, probes):
+    """The modular walk against the measured rate of its own step (one
+    multiply-add mod 2^61 - 1, the 64 x 64 -> 128-bit product from four
+    32 x 32 -> 64 partial products, then two folds), and against the
+    wide-multiply rate: four v_mad_u64_u32 per step at the chip's 39.3e12/s."""
+    best = max(v["term_evals_per_s"] for v in modp.values())
+    avg = float(np.mean([v["term_evals_per_s"] for v in modp.values()]))
+    peak = probes["m61_mac"]["rate"]
+    return {"kernel": "k_eval_m61 (nested walk mod 2^61-1), schemes B/E/H", "bound": "alu",
+            "achieved": avg, "peak": peak, "unit": "mod-2^61-1 multiply-adds/s",
+            "peak_source": "measured: the walk's multiply-add in independent chains (FPE_PROBE_M61_MAC)",
+            "frac": avg / peak, "frac_best_scheme": best / peak,
+            "frac_of_wide_multiply_peak": 4 * avg / FP64_FMA_PEAK}
 
 
 # FP64 operations of one interval step (bounds rounded outward: one fma or
@@ -317,7 +520,9 @@ def compose_phase(fpe, fpe_inputs, torch, dev, reps: int = 3):
             torch.cuda.synchronize()
             ms.append(e0.elapsed_time(e1))
         m = float(np.median(ms))
-        res[s] = {"ms": m, "instances_per_s": b / (m * 1e-3)}
+        macs = compose_macs(t, inp.q.shape[1] - 1) * b
+        res[s] = {"ms": m, "instances_per_s": b / (m * 1e-3), "mod_macs": macs, "mod_macs_per_s": macs / (m * 1e-3),
+                  "frac_of_mad_u64_peak": macs / (m * 1e-3) / FP64_FMA_PEAK}
     return res
 
 
@@ -327,12 +532,16 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--points", type=int, default=10_000_000)
-    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
-    ap.add_argument("--cpu-points", type=int, default=600_000)
-    ap.add_argument("--no-extra", action="store_true", help="skip the served, mod-p and composition phases")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baselines")
+    ap.add_argument("--cpu-points", type=int, default=1_600_000,
+                    help="points of the all-cores CPU baseline sample (the 1-core sample takes a tenth)")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the phases after the timed step (probes, dense, served, mod-p, composition, ...)")
     ap.add_argument("--served-requests", type=int, default=10_000)
     ap.add_argument("--served-only", action="store_true",
                     help="run only the served stream (for a profiler run of the fused kernels) and print its results")
+    ap.add_argument("--probes-only", action="store_true",
+                    help="run only the rate probes (for a profiler run of the probe kernels) and print them")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="after the timed steps, copy a device buffer of this many bytes three times "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -352,10 +561,13 @@ def main():
         served, latency = served_phase(fpe, fpe_inputs, torch, dev, args.served_requests)
         print(json.dumps({"served": {"saturation": served, "poisson": latency}}), flush=True)
         return
+    if args.probes_only:
+        print(json.dumps({"probes": probe_phase(torch, dev)}), flush=True)
+        return
     degrees = (3000, 5000)
     schemes = ("balanced", "estrin", "horner")
     forms = (("f32c", fpe.F32C), ("f64", fpe.F64))
-    inputs, trees, xs, outs, ws, nfb = {}, {}, {}, {}, {}, {}
+    inputs, trees, xs, outs, ws, nfb, conds = {}, {}, {}, {}, {}, {}, {}
     term_evals, df_step_ops = {}, {}
     for n in degrees:
         inp = fpe_inputs.sparse_uni(n, npts=args.points)
@@ -374,21 +586,24 @@ def main():
                     ws[(n, s)] = torch.empty(fpe.workspace_bytes(t, args.points) + 256, dtype=torch.uint8,
                                              device=dev)
                     nfb[(n, s)] = torch.zeros(1, dtype=torch.int64, device=dev)
+                    conds[(n, s)] = torch.empty(args.points, dtype=torch.float32, device=dev)
     keys = list(trees)
     hev = HipEvents()
     ev = {k: [] for k in keys}
 
-    def step(record):
+    # One step: every evaluation of the workload; the compensated ones write
+    # each point's condition number p~(|x|) / |y| beside its value.
+    def step(record, cond=True, evd=ev):
         for k in keys:
             n, s, fname = k
             kw = {}
             if record:
                 e0, e1 = hev.create(), hev.create()
-                ev[k].append((e0, e1))
+                evd[k].append((e0, e1))
                 kw["events"] = (e0, e1)
             if fname == "f32c":
-                fpe.evaluate(trees[k], [xs[n]], out=outs[k], workspace=ws[(n, s)],
-                             nfallback_out=nfb[(n, s)], **kw)
+                fpe.evaluate(trees[k], [xs[n]], out=outs[k], workspace=ws[(n, s)], nfallback_out=nfb[(n, s)],
+                             cond_out=conds[(n, s)] if cond else None, **kw)
             else:
                 fpe.evaluate(trees[k], [xs[n]], out=outs[k], **kw)
 
@@ -416,8 +631,10 @@ def main():
                                            "walk_depth": int(trees[k].info.walk_depth)}
                       for k in keys if k[2] == fname}
 
-    # dominant kernel: the compensated-FP32 walk (most of the step's time)
+    # dominant kernel: the compensated-FP32 walk (most of the step's time),
+    # priced on the algorithmic 11 FP32 operations per term-evaluation
     df_keys = [k for k in keys if k[2] == "f32c"]
+    df_te = sum(term_evals[k] for k in df_keys)
     df_ops = sum(df_step_ops[k] for k in df_keys)
     df_time = sum(walk_ms[k] for k in df_keys) * 1e-3
     f64_keys = [k for k in keys if k[2] == "f64"]
@@ -425,15 +642,17 @@ def main():
     f64_time = sum(walk_ms[k] for k in f64_keys) * 1e-3
     traffic = measured_traffic()
     roofline = {
-        "kernel": "k_eval_df32 (compensated FP32 walk), 6 launches per step",
+        "kernel": "k_eval_df32 (compensated FP32 walk with condition output), 6 launches per step",
         "bound": "alu",
-        "achieved": df_ops / df_time / 1e12,
+        "achieved": DF32_ALG_OPS * df_te / df_time / 1e12,
         "peak": FP32_VALU_PEAK / 1e12,
-        "unit": "TOP/s (FP32 VALU lane-ops)",
-        "frac": (df_ops / df_time) / FP32_VALU_PEAK,
+        "unit": "TFLOP/s (FP32 VALU lane-ops, 11 per term-eval)",
+        "frac": DF32_ALG_OPS * df_te / df_time / FP32_VALU_PEAK,
         "traffic": traffic,
-        "ops_per_term_eval": df_ops / sum(term_evals[k] for k in df_keys),
+        "ops_per_term_eval": DF32_ALG_OPS,
         "avg_launch_ms": df_time * 1e3 / len(df_keys),
+        "walk_ops_per_term_eval": df_ops / df_te,
+        "frac_walk_ops": df_ops / df_time / FP32_VALU_PEAK,
     }
     roofline_f64 = {
         "kernel": "k_eval_f64 (plain FP64 walk), 6 launches per step",
@@ -445,7 +664,22 @@ def main():
         "avg_launch_ms": f64_time * 1e3 / len(f64_keys),
     }
 
-    # accuracy of the last step on a sample (outside the timed region)
+    # the compensated walks again without condition output (outside the
+    # timed region), for comparison
+    ev_nc = {k: [] for k in keys}
+    step(True, cond=False, evd=ev_nc)
+    step(True, cond=False, evd=ev_nc)
+    torch.cuda.synchronize()
+    nc_time = sum(float(np.mean([hev.elapsed_ms(a, b) for a, b in ev_nc[k]])) for k in df_keys) * 1e-3
+    no_cond = {"walk_ms_total": nc_time * 1e3, "frac": DF32_ALG_OPS * df_te / nc_time / FP32_VALU_PEAK,
+               "frac_walk_ops": df_ops / nc_time / FP32_VALU_PEAK}
+
+    # accuracy of the last step on a sample (outside the timed region): the
+    # last step wrote values without condition numbers, so one more step with
+    # them, whose values the sample checks, and whose condition numbers are
+    # compared with the oracle's
+    step(False)
+    torch.cuda.synchronize()
     from oracle import native
     rng = np.random.default_rng(0)
     acc = {}
@@ -462,8 +696,14 @@ def main():
         for s in schemes:
             y32 = outs[(n, s, "f32c")].cpu().numpy()[idx]
             y64 = outs[(n, s, "f64")].cpu().numpy()[idx]
+            cg = conds[(n, s)].cpu().numpy()[idx].astype(np.float64)
+            # the walk's condition numbers against the oracle's, where the
+            # walk stayed in the FP32 range (elsewhere it reports inf / NaN)
+            okc = np.isfinite(cg) & np.isfinite(cond)
             acc[f"n{n}_{s}"] = {"f32c_max_rel_err": float(np.max(np.abs(y32 - ref) / np.abs(ref))),
-                                "f64_max_scaled_err": float(np.max(np.abs(y64 - ref) / pt))}
+                                "f64_max_scaled_err": float(np.max(np.abs(y64 - ref) / pt)),
+                                "f32c_cond_max_rel_dev": float(np.max(np.abs(cg[okc] - cond[okc]) / cond[okc])),
+                                "f32c_cond_finite_frac": float(okc.mean())}
             fb[f"n{n}_{s}"] = nfb[(n, s)].item() / args.points
 
     if args.copy_probe > 0:
@@ -476,17 +716,22 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # free the main workload before the side phases
-    del trees, outs, ws, xs
+    # free the main workload's device buffers before the side phases
+    del trees, outs, ws, xs, conds
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
-    served = latency = modp = compose = ival = big = None
+    probes = dense = served = latency = modp = compose = ival = big = modp_roof = None
     if not args.no_extra:
+        log("rate probes")
+        probes = probe_phase(torch, dev)
+        log("dense degree 1023")
+        dense = dense_phase(fpe, fpe_inputs, torch, dev)
         log("served stream")
         served, latency = served_phase(fpe, fpe_inputs, torch, dev, args.served_requests)
         log("mod-p trivariate")
         modp = modp_phase(fpe, fpe_inputs, torch, dev, hev)
+        modp_roof = modp_roofline(modp, probes)
         log("composition")
         compose = compose_phase(fpe, fpe_inputs, torch, dev)
         log("interval")
@@ -496,26 +741,8 @@ def main():
 
     cpu = None
     if not args.no_cpu:
-        # the CPU oracle as it stands (C, -O2, OpenMP over points): the
-        # double-double Hörner that the compensated results are checked
-        # against and the plain FP64 Hörner, each over the dense coefficient
-        # vector, on the first cpu_points points of both degrees
         log("cpu oracle")
-        native.set_threads(int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1)))
-        cores = native.threads()
-        te = 0.0
-        c0 = time.perf_counter()
-        for n in degrees:
-            xs_c = np.ascontiguousarray(inputs[n].points[: args.cpu_points])
-            nnz = float(np.count_nonzero(inputs[n].coeffs))
-            native.dd_value(inputs[n].coeffs, xs_c)
-            native.horner_f64(inputs[n].coeffs, xs_c, use_fma=False)
-            te += 2 * nnz * len(xs_c)
-        c1 = time.perf_counter()
-        cpu = {"value": te / (c1 - c0), "unit": "term-evals/s", "cores": cores, "kind": "oracle",
-               "sample": f"double-double and plain FP64 Hörner (C, -O2, OpenMP) on the first "
-                         f"{args.cpu_points} points of degrees 3000 and 5000 ({te:.3g} term-evals, "
-                         f"{c1 - c0:.2f} s)"}
+        cpu = cpu_phase(native, fpe_inputs, inputs, degrees, args.cpu_points, args.cpu_points // 10)
 
     out = {
         "metric": "term-evals/sec at stated rel. error vs FP64 oracle; p50/p99 request latency",
@@ -532,18 +759,24 @@ def main():
         "data": "synthetic",
         "config": {"workload": "sparse univariate, degrees 3000 and 5000, 10% zero coefficients, "
                                "1e7 points U[-1.05,1.05]; schemes balanced/Estrin/Hörner; compensated "
-                               "FP32 with FP64 fallback and plain FP64 (12 evaluations per step)",
+                               "FP32 with FP64 fallback and condition numbers, and plain FP64 (12 evaluations "
+                               "per step)",
                    "points": args.points, "term_evals_per_step": total_te},
         "roofline": roofline,
         "roofline_f64": roofline_f64,
-        "cpu_baseline": cpu,
+        "cpu_baseline": None if cpu is None else cpu["all_cores"],
+        "cpu_baselines": cpu,
         "per_evaluation": per,
+        "f32c_without_condition_output": no_cond,
         "accuracy_sampled": acc,
         "condition_sampled": cond_stats,
         "fallback_frac": fb,
         "latency_ms": None if latency is None else {"p50": latency["p50_ms"], "p99": latency["p99_ms"]},
+        "peaks_measured": probes,
+        "dense_1023_1e5": dense,
         "served": None if served is None else {"saturation": served, "poisson": latency},
         "modp_trivariate": modp,
+        "modp_roofline": modp_roof,
         "compose_4096": compose,
         "interval_1e7": ival,
         "bigint_256bit_points": big,
@@ -553,3 +786,10 @@ def main():
 
 if __name__ == "__main__":
     main()
+    # End the process as soon as the line is out: no child process is ever
+    # started, and the interpreter's and the GPU runtime's teardown of the
+    # many GB of device buffers is skipped rather than left running after
+    # the result.
+    sys.stdout.flush()
+    sys.stderr.flush()
+    os._exit(0)

@@ -1,4 +1,5 @@
-"""Builds libfpe.so (HIP kernels for gfx950 + host compiler + C-ABI) in-tree."""
+"""Builds libfpe.so (HIP kernels for gfx950 + host compiler + C-ABI) and the
+rate-probe library libfpe_probe.so, in-tree."""
 from __future__ import annotations
 
 import os
@@ -8,6 +9,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfpe.so")
+PROBE_LIB = os.path.join(HERE, "libfpe_probe.so")
+PROBE_SOURCES = ["probes.hip"]
 SOURCES = ["compile.cpp", "api.cpp", "walk.hip", "eval_f64.hip", "eval_m61.hip", "eval_df32.hip", "eval_iv.hip", "bigint.hip",
            "serve_kernels.hip", "compose.hip", "server.cpp"]
 EXTRA_SOURCES = []
@@ -40,14 +43,16 @@ def build(verbose: bool = False) -> str:
     objs = []
     procs = []
     os.makedirs(os.path.join(HERE, "_build"), exist_ok=True)
-    for src in sources():
+    probe_objs = [os.path.join(HERE, "_build", s + ".o") for s in PROBE_SOURCES]
+    for src in sources() + [os.path.join(CSRC, s) for s in PROBE_SOURCES]:
         obj = os.path.join(HERE, "_build", os.path.basename(src) + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         cmd = [HIPCC] + [f for f in FLAGS if f != "-shared"] + ["-c"] + lang + [src, "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
-        objs.append(obj)
+        if obj not in probe_objs:
+            objs.append(obj)
     failed = []
     for src, p in procs:
         out, _ = p.communicate()
@@ -60,10 +65,11 @@ def build(verbose: bool = False) -> str:
             failed.append(src)
     if failed:
         raise RuntimeError("hipcc failed for: " + ", ".join(failed))
-    tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + objs
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
+    for lib, o in ((LIB, objs), (PROBE_LIB, probe_objs)):
+        tmp = lib + ".tmp"
+        cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp] + o
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, lib)
     return LIB
 
 
