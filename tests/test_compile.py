@@ -329,3 +329,13 @@ def test_deserialize_rejects_corrupt_counts_and_batch():
     with pytest.raises(fpe.FpeError):
         fpe.Tree.deserialize(_set_field(t.serialize(), _OFF_DOMAIN, "<i", fpe.MODP))
     assert fpe.Tree.deserialize(blob).info.batch == 4
+
+
+def test_probe_library_exports_its_header():
+    import ctypes
+    hdr = open(os.path.join(ROOT, "include", "fpe_probe.h")).read()
+    names = set(re.findall(r"^\s*(?:[\w\s\*]+?)\b(fpe_\w+)\s*\(", hdr, flags=re.M))
+    assert names == {"fpe_probe_launch"}
+    L = ctypes.CDLL(os.path.join(ROOT, "paper_1307_5655_amd", "libfpe_probe.so"))
+    for n in names:
+        assert hasattr(L, n), n
