@@ -242,6 +242,27 @@ fpe_status fpe_evaluate_noalloc(const fpe_tree* t, const void* const* pts, int64
  *   workspace  device buffer of fpe_compose_workspace_bytes() bytes */
 size_t fpe_compose_workspace_bytes(const fpe_tree* t, int32_t dq);
 
+/* How the polynomial products of a composition are computed.
+ *   FPE_PRODUCT_FUSED       one wavefront walks one instance, every product a
+ *                           schoolbook convolution (outputs up to 4096 coefficients)
+ *   FPE_PRODUCT_SCHOOLBOOK  the walk op by op, each op one launch over all
+ *                           instances, products by batched schoolbook kernels
+ *   FPE_PRODUCT_NTT         the same walk with every product whose shorter
+ *                           operand has at least 64 coefficients computed
+ *                           exactly by number-theoretic transforms modulo three
+ *                           primes below 2^31 and Garner's recombination
+ *                           (subquadratic products, up to 2^14 coefficients)
+ *   FPE_PRODUCT_AUTO        FUSED when deg_p * dq + 1 <= 4096, else NTT
+ * All give the same residues. */
+typedef enum { FPE_PRODUCT_AUTO = 0, FPE_PRODUCT_FUSED = 1, FPE_PRODUCT_SCHOOLBOOK = 2,
+               FPE_PRODUCT_NTT = 3 } fpe_product;
+size_t fpe_compose_ex_workspace_bytes(const fpe_tree* t, int32_t dq, int32_t product);
+/* fpe_compose with a chosen product method (fpe_compose is FPE_PRODUCT_AUTO).
+ * Errors: as fpe_compose; FPE_EUNSUPPORTED if a transform would exceed 2^14
+ * coefficients or the batch exceeds 65535 instances (op-by-op methods). */
+fpe_status fpe_compose_ex(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, int32_t product,
+                          void* workspace, size_t workspace_bytes, void* stream);
+
 /* Exact evaluation over the natural numbers at big-integer points (the
  * workload of the paper's Benchmarks section, Figure 1): for every point r of
  * the batch, out[r] = p(x_r), with the tree (univariate, FPE_BIGINT, uint64

@@ -110,6 +110,8 @@ def _load():
         "fpe_evaluate_noalloc": ([P, P, i64, P, ctypes.POINTER(EvalOpts), P], i32),
         "fpe_compose_workspace_bytes": ([P, i32], sz),
         "fpe_compose": ([P, P, i32, P, P, sz, P], i32),
+        "fpe_compose_ex_workspace_bytes": ([P, i32, i32], sz),
+        "fpe_compose_ex": ([P, P, i32, P, i32, P, sz, P], i32),
         "fpe_server_workspace_bytes": ([sz], sz),
         "fpe_server_create": ([P, sz, sz, i32, P, ctypes.POINTER(P)], i32),
         "fpe_server_submit": ([P, ctypes.POINTER(Request), ctypes.POINTER(u64)], i32),
@@ -136,7 +138,8 @@ EXPORTED = ["fpe_last_error", "fpe_version", "fpe_compile", "fpe_tree_free", "fp
             "fpe_tree_get_info", "fpe_tree_node_exps", "fpe_tree_device_bytes", "fpe_tree_upload",
             "fpe_tree_serialize", "fpe_tree_deserialize", "fpe_workspace_bytes", "fpe_evaluate",
             "fpe_evaluate_noalloc",
-            "fpe_compose_workspace_bytes", "fpe_compose", "fpe_server_workspace_bytes", "fpe_server_create",
+            "fpe_compose_workspace_bytes", "fpe_compose", "fpe_compose_ex_workspace_bytes", "fpe_compose_ex",
+            "fpe_server_workspace_bytes", "fpe_server_create",
             "fpe_server_submit",
             "fpe_server_poll", "fpe_server_wait", "fpe_server_drain", "fpe_server_stats",
             "fpe_server_destroy", "fpe_bigint_out_limbs", "fpe_bigint_workspace_bytes", "fpe_eval_bigint",
@@ -376,24 +379,39 @@ def eval_bigint(tree: Tree, x, lout=None, out=None, workspace=None, stream=None,
     return out
 
 
-def compose(tree: Tree, q, out=None, workspace=None, stream=None):
+PRODUCT_AUTO, PRODUCT_FUSED, PRODUCT_SCHOOLBOOK, PRODUCT_NTT = 0, 1, 2, 3
+PRODUCTS = {"auto": PRODUCT_AUTO, "fused": PRODUCT_FUSED, "schoolbook": PRODUCT_SCHOOLBOOK, "ntt": PRODUCT_NTT}
+
+
+def compose_workspace_bytes(tree: Tree, dq: int, product=PRODUCT_AUTO) -> int:
+    product = PRODUCTS.get(product, product)
+    return int(lib.fpe_compose_ex_workspace_bytes(tree.handle, dq, product))
+
+
+def compose(tree: Tree, q, out=None, workspace=None, stream=None, product=PRODUCT_AUTO):
     """p_r(q_r(x)) mod 2^31-1 for every instance r compiled into ``tree``;
-    ``q`` is a device int32/uint32 tensor [batch, dq + 1]."""
+    ``q`` is a device int32/uint32 tensor [batch, dq + 1]; ``product`` picks
+    how the polynomial products are computed (fpe_compose_ex)."""
     import torch
     if tree._dev is None:
         raise FpeError(-1, "tree is not uploaded")
+    product = PRODUCTS.get(product, product)
     batch, dq1 = q.shape
     dq = dq1 - 1
     dp = int(tree.node_exps().max())
+    if batch != tree.batch or not q.is_contiguous() or q.element_size() != 4:
+        raise FpeError(-1, "q must be a contiguous 32-bit tensor [batch, dq + 1]")
     if out is None:
         out = torch.empty((batch, dp * dq + 1), dtype=torch.int32, device=q.device)
-    need = int(lib.fpe_compose_workspace_bytes(tree.handle, dq))
+    elif out.numel() < batch * (dp * dq + 1) or not out.is_contiguous() or out.element_size() != 4:
+        raise FpeError(-1, "out must be a contiguous 32-bit tensor [batch, deg_p * dq + 1]")
+    need = compose_workspace_bytes(tree, dq, product)
     if workspace is None:
         workspace = torch.empty(need + 256, dtype=torch.uint8, device=q.device)
     off = (-workspace.data_ptr()) % 256
-    _check(lib.fpe_compose(tree.handle, ctypes.c_void_p(q.data_ptr()), dq,
-                           ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(workspace.data_ptr() + off),
-                           workspace.numel() - off, _stream_ptr(stream)))
+    _check(lib.fpe_compose_ex(tree.handle, ctypes.c_void_p(q.data_ptr()), dq, ctypes.c_void_p(out.data_ptr()),
+                              product, ctypes.c_void_p(workspace.data_ptr() + off), workspace.numel() - off,
+                              _stream_ptr(stream)))
     return out
 
 

@@ -390,6 +390,21 @@ fpe_status fpe_bigint_status(const void* workspace, void* stream) {
   return FPE_OK;
 }
 
+size_t fpe_compose_ex_workspace_bytes(const fpe_tree* t, int32_t dq, int32_t product) {
+  return compose_workspace_bytes_ex(t, dq, product);
+}
+
+fpe_status fpe_compose_ex(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, int32_t product,
+                          void* workspace, size_t workspace_bytes, void* stream) {
+  if (!t || !q || !out) return fail(FPE_EINVAL, "NULL argument");
+  if (!t->dev) return fail(FPE_EINVAL, "tree is not uploaded");
+  if (t->domain != FPE_MODP || t->modulus != kP31 || t->nvars != 1)
+    return fail(FPE_EINVAL, "composition needs a univariate tree compiled mod 2^31-1");
+  if (dq < 1) return fail(FPE_EINVAL, "deg q must be >= 1");
+  if (product < FPE_PRODUCT_AUTO || product > FPE_PRODUCT_NTT) return fail(FPE_EINVAL, "unknown product method");
+  return launch_compose_ex(t, q, dq, out, workspace, workspace_bytes, product, stream);
+}
+
 fpe_status fpe_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* workspace,
                        size_t workspace_bytes, void* stream) {
   if (!t || !q || !out) return fail(FPE_EINVAL, "NULL argument");

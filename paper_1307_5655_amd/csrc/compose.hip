@@ -234,7 +234,7 @@ __global__ __launch_bounds__(kCB) void k_compose_walk(ComposeArgs A) {
 
 }  // namespace
 
-size_t compose_workspace_bytes(const fpe_tree* t, int32_t dq) {
+size_t compose_fused_workspace_bytes(const fpe_tree* t, int32_t dq) {
   if (!t || t->nodes.empty() || dq < 1) return 0;
   int32_t dp = 0;
   for (size_t i = 0; i < t->nodes.size(); ++i) dp = std::max(dp, t->exps[i * t->nvars]);
@@ -243,11 +243,11 @@ size_t compose_workspace_bytes(const fpe_tree* t, int32_t dq) {
   return (size_t)(per * t->batch) * sizeof(uint32_t);
 }
 
-fpe_status launch_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* ws,
-                          size_t ws_bytes, void* stream) {
+fpe_status launch_compose_fused(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* ws,
+                                size_t ws_bytes, void* stream) {
   if (t->n_offtable > 0) return fail(FPE_EUNSUPPORTED, "composition needs every power in the table");
   if (t->depth + 2 > kMaxDepth + 2) return fail(FPE_EUNSUPPORTED, "walk deeper than the kernels hold");
-  const size_t need = compose_workspace_bytes(t, dq);
+  const size_t need = compose_fused_workspace_bytes(t, dq);
   if (!ws || ws_bytes < need) return fail(FPE_ENOMEM, "workspace smaller than fpe_compose_workspace_bytes()");
   if (t->batch > 0x7fffffff) return fail(FPE_EINVAL, "batch too large");
   ComposeArgs A{};
@@ -266,6 +266,45 @@ fpe_status launch_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("compose launch: ") + hipGetErrorString(e));
   return FPE_OK;
+}
+
+// The product method of a composition: the fused walk (one wavefront per
+// instance, all products schoolbook) for outputs that fit its design, and
+// the op-by-op walk with transform products beyond.
+constexpr int64_t kFusedMaxOut = 4096;
+constexpr int32_t kNttMinOperand = 64;
+int32_t compose_method(const fpe_tree* t, int32_t dq, int32_t product) {
+  if (product != FPE_PRODUCT_AUTO) return product;
+  int32_t dp = 0;
+  for (size_t i = 0; i < t->nodes.size(); ++i) dp = std::max(dp, t->exps[i * t->nvars]);
+  return (int64_t)dp * dq + 1 <= kFusedMaxOut ? FPE_PRODUCT_FUSED : FPE_PRODUCT_NTT;
+}
+
+size_t compose_workspace_bytes_ex(const fpe_tree* t, int32_t dq, int32_t product) {
+  if (!t || dq < 1) return 0;
+  switch (compose_method(t, dq, product)) {
+    case FPE_PRODUCT_FUSED: return compose_fused_workspace_bytes(t, dq);
+    case FPE_PRODUCT_SCHOOLBOOK: return compose_ops_workspace_bytes(t, dq, 1 << 30);
+    case FPE_PRODUCT_NTT: return compose_ops_workspace_bytes(t, dq, kNttMinOperand);
+  }
+  return 0;
+}
+size_t compose_workspace_bytes(const fpe_tree* t, int32_t dq) {
+  return compose_workspace_bytes_ex(t, dq, FPE_PRODUCT_AUTO);
+}
+
+fpe_status launch_compose_ex(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* ws,
+                             size_t ws_bytes, int32_t product, void* stream) {
+  switch (compose_method(t, dq, product)) {
+    case FPE_PRODUCT_FUSED: return launch_compose_fused(t, q, dq, out, ws, ws_bytes, stream);
+    case FPE_PRODUCT_SCHOOLBOOK: return launch_compose_ops(t, q, dq, out, ws, ws_bytes, 1 << 30, stream);
+    case FPE_PRODUCT_NTT: return launch_compose_ops(t, q, dq, out, ws, ws_bytes, kNttMinOperand, stream);
+  }
+  return fail(FPE_EINVAL, "unknown product method");
+}
+fpe_status launch_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* ws,
+                          size_t ws_bytes, void* stream) {
+  return launch_compose_ex(t, q, dq, out, ws, ws_bytes, FPE_PRODUCT_AUTO, stream);
 }
 
 }  // namespace fpe

@@ -232,6 +232,14 @@ size_t eval_workspace_bytes(const fpe_tree* t, int64_t npts);
 fpe_status launch_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out,
                           void* ws, size_t ws_bytes, void* stream);
 size_t compose_workspace_bytes(const fpe_tree* t, int32_t dq);
+size_t compose_workspace_bytes_ex(const fpe_tree* t, int32_t dq, int32_t product);
+fpe_status launch_compose_ex(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* ws,
+                             size_t ws_bytes, int32_t product, void* stream);
+// the composition walk op by op with batched launches (ntt.hip); products
+// whose shorter operand has at least ntt_min coefficients use transforms
+size_t compose_ops_workspace_bytes(const fpe_tree* t, int32_t dq, int32_t ntt_min);
+fpe_status launch_compose_ops(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* ws,
+                              size_t ws_bytes, int32_t ntt_min, void* stream);
 fpe_status launch_bigint(const fpe_tree* t, const uint32_t* x, int32_t lx, int64_t batch, uint32_t* out,
                          int32_t lout, void* ws, size_t ws_bytes, void* stream);
 size_t bigint_workspace_bytes(const fpe_tree* t, int32_t lout, int64_t batch);

@@ -81,3 +81,52 @@ def test_compose_full_size_schwartz_zippel(dev):
         idx = [0, 1, 2047, 4095]
         want = native.compose_modp(inp.p[idx], inp.q[idx], P31)
         assert np.array_equal(got[idx], want)
+
+
+def gpu_compose_method(P, Q, scheme, dev, product):
+    b, dp1 = P.shape
+    ex = np.arange(dp1, dtype=np.int32).reshape(-1, 1)
+    t = fpe.Tree(ex, P.astype(np.uint64), scheme, fpe.MODP, P31).upload(dev)
+    q = torch.from_numpy(np.ascontiguousarray(Q.astype(np.int32))).to(dev)
+    out = fpe.compose(t, q, product=product)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint32)
+
+
+@pytest.mark.parametrize("scheme", ["balanced", "estrin", "horner", "balanced_floor"])
+def test_compose_product_methods_agree_exactly(dev, scheme):
+    """The fused walk, the op-by-op walk with schoolbook products and the
+    op-by-op walk with transform products give the same residues, equal to
+    the oracle's expansion (sparse p with a zero constant term included)."""
+    say(f"compose product methods {scheme}")
+    g = np.random.default_rng([13075655, 930])
+    for b, dp, dq in [(37, 255, 15), (9, 130, 7), (5, 64, 63), (4, 300, 1)]:
+        P = g.integers(0, P31, size=(b, dp + 1), dtype=np.uint32)
+        P[:, 0] = 0
+        P[:, g.choice(dp, dp // 10, replace=False)] = 0
+        Q = g.integers(0, P31, size=(b, dq + 1), dtype=np.uint32)
+        got = {m: gpu_compose_method(P, Q, scheme, dev, m) for m in ("fused", "schoolbook", "ntt")}
+        assert np.array_equal(got["fused"], got["ntt"]), (b, dp, dq)
+        assert np.array_equal(got["fused"], got["schoolbook"]), (b, dp, dq)
+        want = native.compose_modp(P[:3], Q[:3], P31)
+        assert np.array_equal(got["ntt"][:3], want), (b, dp, dq)
+
+
+def test_compose_ntt_beyond_the_fused_walk(dev):
+    """Outputs longer than the fused walk takes (deg 1023 o 15: 15,346
+    coefficients) go to the transform products: exact against the oracle on
+    two instances, Schwartz-Zippel on all, the same for every scheme."""
+    say("compose 12 x (1023 o 15) by transforms")
+    g = np.random.default_rng([13075655, 931])
+    P = g.integers(0, P31, size=(12, 1024), dtype=np.uint32)
+    Q = g.integers(0, P31, size=(12, 16), dtype=np.uint32)
+    res = {s: gpu_compose_method(P, Q, s, dev, "auto") for s in ("balanced", "estrin", "horner")}
+    assert res["balanced"].shape == (12, 1023 * 15 + 1)
+    assert np.array_equal(res["balanced"], res["estrin"]) and np.array_equal(res["balanced"], res["horner"])
+    want = native.compose_modp(P[:2], Q[:2], P31)
+    assert np.array_equal(res["balanced"][:2], want)
+    rng = np.random.default_rng(3)
+    for b in range(12):
+        t = int(rng.integers(2, P31 - 1))
+        assert ocomp.horner_at(res["balanced"][b].tolist(), t, P31) == \
+            ocomp.compose_at(P[b].tolist(), Q[b].tolist(), t, P31), b
