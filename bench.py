@@ -526,6 +526,55 @@ def compose_phase(fpe, fpe_inputs, torch, dev, reps: int = 3):
     return res
 
 
+def compose_methods_phase(fpe, fpe_inputs, torch, dev, reps: int = 3):
+    """Composition by product method: the 4096 x (255 o 15) workload with the
+    fused walk, and with the op-by-op walk using schoolbook or transform
+    (subquadratic) products; then larger compositions (64 instances of
+    degree 511, 512 and 1023 in p, degree 15 in q), where the transform
+    products make the divide-and-conquer schemes pay off against Hörner and
+    the term count just past a power of two shows Estrin's staircase."""
+    res = {}
+
+    def timed(t, q, product):
+        out = fpe.compose(t, q, product=product)
+        ws = torch.empty(fpe.compose_workspace_bytes(t, q.shape[1] - 1, product) + 256, dtype=torch.uint8,
+                         device=dev)
+        fpe.compose(t, q, out=out, workspace=ws, product=product)
+        torch.cuda.synchronize()
+        ms = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fpe.compose(t, q, out=out, workspace=ws, product=product)
+            e1.record()
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    inp = fpe_inputs.compose_batch()
+    q = torch.from_numpy(np.ascontiguousarray(inp.q.astype(np.int32))).to(dev)
+    ex = np.arange(inp.p.shape[1], dtype=np.int32).reshape(-1, 1)
+    c4 = {}
+    for s in ("balanced", "estrin", "horner"):
+        t = fpe.Tree(ex, inp.p.astype(np.uint64), s, fpe.MODP, fpe.P31).upload(dev)
+        c4[s] = {m: timed(t, q, m) for m in ("fused", "schoolbook", "ntt")}
+    res["4096x255o15_ms"] = c4
+    g = np.random.default_rng([13075655, 940])
+    for dp in (511, 512, 1023):
+        P = g.integers(0, fpe.P31, size=(64, dp + 1), dtype=np.uint32).astype(np.uint64)
+        Q = torch.from_numpy(g.integers(0, fpe.P31, size=(64, 16), dtype=np.uint32).astype(np.int32)).to(dev)
+        exd = np.arange(dp + 1, dtype=np.int32).reshape(-1, 1)
+        row = {}
+        for s in ("balanced", "estrin", "horner"):
+            t = fpe.Tree(exd, P, s, fpe.MODP, fpe.P31).upload(dev)
+            row[s] = {m: timed(t, Q, m) for m in ("schoolbook", "ntt")}
+        row["estrin_over_balanced_ntt"] = row["estrin"]["ntt"] / row["balanced"]["ntt"]
+        row["horner_over_balanced_ntt"] = row["horner"]["ntt"] / row["balanced"]["ntt"]
+        res[f"64x{dp}o15_ms"] = row
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -721,7 +770,7 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
-    probes = dense = served = latency = modp = compose = ival = big = modp_roof = None
+    probes = dense = served = latency = modp = compose = ival = big = modp_roof = compose_methods = None
     if not args.no_extra:
         log("rate probes")
         probes = probe_phase(torch, dev)
@@ -734,6 +783,8 @@ def main():
         modp_roof = modp_roofline(modp, probes)
         log("composition")
         compose = compose_phase(fpe, fpe_inputs, torch, dev)
+        log("composition by product method")
+        compose_methods = compose_methods_phase(fpe, fpe_inputs, torch, dev)
         log("interval")
         ival = interval_phase(fpe, fpe_inputs, torch, dev, hev, args.points)
         log("big integers")
@@ -778,6 +829,7 @@ def main():
         "modp_trivariate": modp,
         "modp_roofline": modp_roof,
         "compose_4096": compose,
+        "compose_by_product_method": compose_methods,
         "interval_1e7": ival,
         "bigint_256bit_points": big,
     }
