@@ -497,6 +497,39 @@ def bigint_phase(fpe, torch, dev, reps: int = 3):
     return res
 
 
+def bigpoint_phase(fpe, torch, dev, reps: int = 3):
+    """The Benchmarks section's setting: one polynomial (64-bit coefficients)
+    at ONE point of 512 bits, term counts at and just past 128 and 256; time
+    per scheme and the ratio to the balanced scheme (the form of Figure 1)."""
+    g = np.random.default_rng([13075655, 9])
+    lx = 32
+    x = torch.from_numpy(g.integers(0, 1 << 16, size=lx, dtype=np.int64).astype(np.int32)).to(dev)
+    res = {}
+    for n in (127, 128, 129, 255, 256, 257):
+        ex = np.arange(n + 1, dtype=np.int32).reshape(-1, 1)
+        co = g.integers(1, 2 ** 63, n + 1, dtype=np.uint64)
+        row = {}
+        for s in ("balanced", "estrin", "horner"):
+            t = fpe.Tree(ex, co, s, fpe.BIGINT).upload(dev)
+            out = fpe.eval_bigpoint(t, x)
+            ws = torch.empty(int(fpe.lib.fpe_bigpoint_workspace_bytes(t.handle, lx)) + 256, dtype=torch.uint8,
+                             device=dev)
+            fpe.eval_bigpoint(t, x, out=out, workspace=ws)
+            ms = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fpe.eval_bigpoint(t, x, out=out, workspace=ws, check=False)
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            row[s] = float(np.median(ms))
+        res[f"terms{n + 1}"] = {"ms": row, "estrin_over_balanced": row["estrin"] / row["balanced"],
+                                "horner_over_balanced": row["horner"] / row["balanced"]}
+    return res
+
+
 def compose_phase(fpe, fpe_inputs, torch, dev, reps: int = 3):
     """4096 instances of p(q(x)) mod 2^31-1, deg p = 255, deg q = 15."""
     inp = fpe_inputs.compose_batch()
@@ -770,7 +803,7 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
-    probes = dense = served = latency = modp = compose = ival = big = modp_roof = compose_methods = None
+    probes = dense = served = latency = modp = compose = ival = big = modp_roof = compose_methods = bigpoint = None
     if not args.no_extra:
         log("rate probes")
         probes = probe_phase(torch, dev)
@@ -789,6 +822,8 @@ def main():
         ival = interval_phase(fpe, fpe_inputs, torch, dev, hev, args.points)
         log("big integers")
         big = bigint_phase(fpe, torch, dev)
+        log("one big point")
+        bigpoint = bigpoint_phase(fpe, torch, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -832,6 +867,7 @@ def main():
         "compose_by_product_method": compose_methods,
         "interval_1e7": ival,
         "bigint_256bit_points": big,
+        "bigint_one_512bit_point": bigpoint,
     }
     print(json.dumps(out), flush=True)
 

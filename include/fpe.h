@@ -281,8 +281,33 @@ int32_t fpe_bigint_out_limbs(const fpe_tree* t, int32_t lx);
 size_t fpe_bigint_workspace_bytes(const fpe_tree* t, int32_t lout, int64_t batch);
 fpe_status fpe_eval_bigint(const fpe_tree* t, const uint32_t* x, int32_t lx, int64_t batch, uint32_t* out,
                            int32_t lout, void* workspace, size_t workspace_bytes, void* stream);
+/* Exact evaluation at ONE big natural number x (the setting of the Benchmarks
+ * section, Figure 1: one polynomial, one large point).  The tree (univariate,
+ * FPE_BIGINT, uint64 coefficients) is walked level by level from its
+ * definition (Section 1): u(N) = c(N) + sum_C u(C) x^{d(C)}, p(x) = u(R) x^{d(R)};
+ * the nodes of one height are independent (the divide-and-conquer
+ * parallelism of Section 2.3) and run as batched launches, the powers x^d
+ * first, by the tree's chain (Section 2.2).  Products of big integers are
+ * exact convolutions of 16-bit limbs by number-theoretic transforms (two
+ * primes below 2^31, Garner's recombination) or schoolbook when an operand
+ * has fewer than 64 limbs; sums are normalised by a parallel carry-lookahead.
+ *   x    device uint32[lx]: the point's 16-bit limbs (values < 2^16), least
+ *        significant first
+ *   out  device uint32[lout]: p(x)'s limbs, zero-padded;
+ *        lout >= fpe_bigpoint_out_limbs(t, lx) (0: a product would exceed 2^14
+ *        limbs, unsupported)
+ *   workspace  device buffer of fpe_bigpoint_workspace_bytes(t, lx) bytes,
+ *        256-byte aligned; its first 4 bytes are the overflow flag that
+ *        fpe_bigint_status reads
+ * The schedule (which products and sums each level runs) is built on the host
+ * at the first call for a tree and point length and kept with the tree.
+ * Errors: FPE_EINVAL, FPE_ENOMEM (workspace), FPE_EUNSUPPORTED. */
+int64_t fpe_bigpoint_out_limbs(const fpe_tree* t, int32_t lx);
+size_t fpe_bigpoint_workspace_bytes(const fpe_tree* t, int32_t lx);
+fpe_status fpe_eval_bigpoint(const fpe_tree* t, const uint32_t* x, int32_t lx, uint32_t* out, int64_t lout,
+                             void* workspace, size_t workspace_bytes, void* stream);
 /* Waits for stream, then reads the overflow flag that the last fpe_eval_bigint
- * on this workspace wrote (a value needed more than lout limbs, which the
+ * or fpe_eval_bigpoint on this workspace wrote (a value needed more than lout limbs, which the
  * host's lout bound rules out; a device-side check).  FPE_OK, or FPE_ENOMEM
  * if the result was truncated.  This call synchronises; fpe_eval_bigint does not. */
 fpe_status fpe_bigint_status(const void* workspace, void* stream);

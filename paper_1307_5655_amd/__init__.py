@@ -124,6 +124,9 @@ def _load():
         "fpe_bigint_workspace_bytes": ([P, i32, i64], sz),
         "fpe_eval_bigint": ([P, P, i32, i64, P, i32, P, sz, P], i32),
         "fpe_bigint_status": ([P, P], i32),
+        "fpe_bigpoint_out_limbs": ([P, i32], i64),
+        "fpe_bigpoint_workspace_bytes": ([P, i32], sz),
+        "fpe_eval_bigpoint": ([P, P, i32, P, i64, P, sz, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -143,7 +146,7 @@ EXPORTED = ["fpe_last_error", "fpe_version", "fpe_compile", "fpe_tree_free", "fp
             "fpe_server_submit",
             "fpe_server_poll", "fpe_server_wait", "fpe_server_drain", "fpe_server_stats",
             "fpe_server_destroy", "fpe_bigint_out_limbs", "fpe_bigint_workspace_bytes", "fpe_eval_bigint",
-            "fpe_bigint_status"]
+            "fpe_bigint_status", "fpe_bigpoint_out_limbs", "fpe_bigpoint_workspace_bytes", "fpe_eval_bigpoint"]
 
 
 def _check(st: int):
@@ -381,6 +384,37 @@ def eval_bigint(tree: Tree, x, lout=None, out=None, workspace=None, stream=None,
 
 PRODUCT_AUTO, PRODUCT_FUSED, PRODUCT_SCHOOLBOOK, PRODUCT_NTT = 0, 1, 2, 3
 PRODUCTS = {"auto": PRODUCT_AUTO, "fused": PRODUCT_FUSED, "schoolbook": PRODUCT_SCHOOLBOOK, "ntt": PRODUCT_NTT}
+
+
+def eval_bigpoint(tree: Tree, x, out=None, workspace=None, stream=None, check=True):
+    """p(x) over the natural numbers at ONE big point: ``x`` is a device int32
+    tensor [lx] of 16-bit limbs (least significant first); the result is a
+    tensor [fpe_bigpoint_out_limbs] of int32 limbs (values < 2^16).  With
+    ``check`` the overflow flag is read back (fpe_bigint_status, which waits
+    for the stream)."""
+    import torch
+    if tree._dev is None:
+        raise FpeError(-1, "tree is not uploaded")
+    if x.dim() != 1 or not x.is_contiguous() or x.element_size() != 4:
+        raise FpeError(-1, "x must be a contiguous 32-bit tensor [lx]")
+    lx = x.numel()
+    lout = int(lib.fpe_bigpoint_out_limbs(tree.handle, lx))
+    if lout <= 0:
+        raise FpeError(-5, (lib.fpe_last_error() or b"").decode() or "unsupported size")
+    if out is None:
+        out = torch.empty(lout, dtype=torch.int32, device=x.device)
+    elif out.numel() < lout or not out.is_contiguous() or out.element_size() != 4:
+        raise FpeError(-1, f"out must be a contiguous 32-bit tensor of at least {lout} limbs")
+    need = int(lib.fpe_bigpoint_workspace_bytes(tree.handle, lx))
+    if workspace is None:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=x.device)
+    off = (-workspace.data_ptr()) % 256
+    _check(lib.fpe_eval_bigpoint(tree.handle, ctypes.c_void_p(x.data_ptr()), lx, ctypes.c_void_p(out.data_ptr()),
+                                 out.numel(), ctypes.c_void_p(workspace.data_ptr() + off), workspace.numel() - off,
+                                 _stream_ptr(stream)))
+    if check:
+        _check(lib.fpe_bigint_status(ctypes.c_void_p(workspace.data_ptr() + off), _stream_ptr(stream)))
+    return out
 
 
 def compose_workspace_bytes(tree: Tree, dq: int, product=PRODUCT_AUTO) -> int:

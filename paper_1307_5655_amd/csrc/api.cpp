@@ -89,7 +89,11 @@ fpe_status fpe_compile(int32_t nvars, int64_t nterms, const int32_t* exps, const
   }
 }
 
-void fpe_tree_free(fpe_tree* t) { delete t; }
+void fpe_tree_free(fpe_tree* t) {
+  if (!t) return;
+  bigpoint_forget(t);
+  delete t;
+}
 
 fpe_status fpe_tree_nodes(const fpe_tree* t, const fpe_node** nodes, int64_t* n, int32_t* max_slot) {
   if (!t) return fail(FPE_EINVAL, "tree is NULL");
@@ -378,6 +382,25 @@ fpe_status fpe_eval_bigint(const fpe_tree* t, const uint32_t* x, int32_t lx, int
   if (lout > kBigMaxLimbs) return fail(FPE_EUNSUPPORTED, "more output limbs than the kernel's columns hold");
   if (lout < bigint_limbs_needed(t, lx)) return fail(FPE_EINVAL, "lout smaller than fpe_bigint_out_limbs()");
   return launch_bigint(t, x, lx, batch, out, lout, workspace, workspace_bytes, stream);
+}
+
+int64_t fpe_bigpoint_out_limbs(const fpe_tree* t, int32_t lx) {
+  if (!t || t->domain != FPE_BIGINT || lx < 1) return 0;
+  return bigpoint_out_limbs(t, lx);
+}
+
+size_t fpe_bigpoint_workspace_bytes(const fpe_tree* t, int32_t lx) {
+  if (!t || t->domain != FPE_BIGINT || lx < 1) return 0;
+  return bigpoint_workspace_bytes(t, lx);
+}
+
+fpe_status fpe_eval_bigpoint(const fpe_tree* t, const uint32_t* x, int32_t lx, uint32_t* out, int64_t lout,
+                             void* workspace, size_t workspace_bytes, void* stream) {
+  if (!t || !x || !out) return fail(FPE_EINVAL, "NULL argument");
+  if (!t->dev) return fail(FPE_EINVAL, "tree is not uploaded");
+  if (t->domain != FPE_BIGINT) return fail(FPE_EINVAL, "the tree is not compiled for FPE_BIGINT");
+  if (lx < 1) return fail(FPE_EINVAL, "the point needs at least one limb");
+  return launch_bigpoint(t, x, lx, out, lout, workspace, workspace_bytes, stream);
 }
 
 fpe_status fpe_bigint_status(const void* workspace, void* stream) {

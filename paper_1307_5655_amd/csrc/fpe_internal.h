@@ -243,6 +243,12 @@ fpe_status launch_compose_ops(const fpe_tree* t, const uint32_t* q, int32_t dq, 
 fpe_status launch_bigint(const fpe_tree* t, const uint32_t* x, int32_t lx, int64_t batch, uint32_t* out,
                          int32_t lout, void* ws, size_t ws_bytes, void* stream);
 size_t bigint_workspace_bytes(const fpe_tree* t, int32_t lout, int64_t batch);
+// evaluation at one big point (bigpoint.hip); its schedule is cached per tree
+int64_t bigpoint_out_limbs(const fpe_tree* t, int32_t lx);
+size_t bigpoint_workspace_bytes(const fpe_tree* t, int32_t lx);
+fpe_status launch_bigpoint(const fpe_tree* t, const uint32_t* x, int32_t lx, uint32_t* out, int64_t lout, void* ws,
+                           size_t ws_bytes, void* stream);
+void bigpoint_forget(const fpe_tree* t);
 constexpr int kMaxDepth = 15;   // stack depth the kernels hold (the code's 4-bit level field)
 constexpr int kBigMaxLimbs = 1 << 16;   // big-integer values: columns of 2^16 limb products fit in 64 bits
 constexpr int kMaxTable = 48;   // power-table entries held per point (composition)

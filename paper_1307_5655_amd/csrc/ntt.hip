@@ -27,73 +27,11 @@
 #include <algorithm>
 
 #include "fpe_internal.h"
+#include "ntt_core.h"
 
 namespace fpe {
 
 namespace {
-
-constexpr int kNttLogMax = 14;
-constexpr int kNttMax = 1 << kNttLogMax;   // largest transform length (LDS: 4 bytes per word, 64 KB)
-constexpr int kNttThreads = 1024;
-
-struct NttPrime {
-  uint32_t p, pinv, r2, g;   // pinv = -p^-1 mod 2^32, r2 = 2^64 mod p, g a generator
-};
-constexpr uint32_t neg_inv32(uint32_t p) {
-  uint32_t x = p;   // Newton's iteration for p^-1 mod 2^32 (p odd)
-  for (int i = 0; i < 5; ++i) x *= 2u - p * x;
-  return 0u - x;
-}
-constexpr uint32_t r2_mod(uint32_t p) {
-  const uint64_t r = ((uint64_t)1 << 32) % p;
-  return (uint32_t)((r * r) % p);
-}
-constexpr NttPrime make_prime(uint32_t p, uint32_t g) { return NttPrime{p, neg_inv32(p), r2_mod(p), g}; }
-constexpr NttPrime kPrimes[3] = {make_prime(2113929217u, 5u), make_prime(2013265921u, 31u),
-                                 make_prime(1811939329u, 13u)};
-
-__device__ __forceinline__ uint32_t mmul(uint32_t a, uint32_t b, uint32_t p, uint32_t pinv) {
-  const uint64_t t = (uint64_t)a * b;
-  const uint32_t m = (uint32_t)t * pinv;
-  const uint32_t r = (uint32_t)((t + (uint64_t)m * p) >> 32);
-  return r >= p ? r - p : r;
-}
-__device__ __forceinline__ uint32_t madd(uint32_t a, uint32_t b, uint32_t p) {
-  const uint32_t s = a + b;
-  return s >= p ? s - p : s;
-}
-__device__ __forceinline__ uint32_t msub(uint32_t a, uint32_t b, uint32_t p) { return a >= b ? a - b : a + p - b; }
-
-uint64_t host_pow(uint64_t b, uint64_t e, uint64_t m) {
-  uint64_t r = 1 % m;
-  b %= m;
-  while (e) {
-    if (e & 1) r = (uint64_t)((unsigned __int128)r * b % m);
-    b = (uint64_t)((unsigned __int128)b * b % m);
-    e >>= 1;
-  }
-  return r;
-}
-
-// Twiddle tables of one prime: tw[k] = w^k and tw[kNttMax / 2 + k] = w^-k
-// (k < kNttMax / 2) in Montgomery form, w a primitive kNttMax-th root.
-__global__ void k_twiddles(uint32_t* tw, uint32_t w, uint32_t winv, int prime) {
-  const NttPrime P = kPrimes[prime];
-  const int k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= kNttMax / 2) return;
-  uint32_t acc = mmul(1u, P.r2, P.p, P.pinv), acci = acc;
-  uint32_t b = mmul(w, P.r2, P.p, P.pinv), bi = mmul(winv, P.r2, P.p, P.pinv);
-  for (int e = k; e; e >>= 1) {
-    if (e & 1) {
-      acc = mmul(acc, b, P.p, P.pinv);
-      acci = mmul(acci, bi, P.p, P.pinv);
-    }
-    b = mmul(b, b, P.p, P.pinv);
-    bi = mmul(bi, bi, P.p, P.pinv);
-  }
-  tw[k] = acc;
-  tw[kNttMax / 2 + k] = acci;
-}
 
 // Forward transform of row blockIdx.x (src + row * src_stride, `len`
 // residues < 2^31, zero-padded to n) modulo prime blockIdx.y, into
@@ -131,9 +69,6 @@ __global__ __launch_bounds__(kNttThreads) void k_ntt_fwd(const uint32_t* __restr
 // Pointwise product of the transforms a (row blockIdx.x) and b (row
 // blockIdx.x, or row 0 when b_rows == 1), then the inverse transform, scaled
 // so that the result is the cyclic convolution itself; into c.
-struct Scales {
-  uint32_t s[3];   // n^-1 R^2 mod p for each prime
-};
 __global__ __launch_bounds__(kNttThreads) void k_ntt_mul_inv(const uint32_t* __restrict__ a,
                                                              const uint32_t* __restrict__ b, int b_rows, int n,
                                                              int logn, Scales sc, const uint32_t* __restrict__ tw_all,
@@ -349,16 +284,6 @@ Plan make_plan(const fpe_tree* t, int32_t dq, int ntt_min) {
   return P;
 }
 
-Scales scales_for(int n) {
-  Scales sc{};
-  for (int k = 0; k < 3; ++k) {
-    const uint64_t p = kPrimes[k].p;
-    const uint64_t ninv = host_pow((uint64_t)n, p - 2, p);
-    sc.s[k] = (uint32_t)((unsigned __int128)ninv * kPrimes[k].r2 % p);
-  }
-  return sc;
-}
-
 CrtConst crt_consts() {
   const uint64_t p1 = kPrimes[0].p, p2 = kPrimes[1].p, p3 = kPrimes[2].p;
   auto mont = [](uint64_t v, const NttPrime& P) {   // v R mod p
@@ -423,16 +348,7 @@ struct Runner {
 
   void run(const uint32_t* q, int32_t dq, uint32_t* out) {
     K = crt_consts();
-    if (P.nmax) {
-      uint32_t* tw = (uint32_t*)(ws + P.off_tw);
-      for (int k = 0; k < 3; ++k) {
-        const uint64_t p = kPrimes[k].p;
-        const uint64_t w = host_pow(kPrimes[k].g, (p - 1) / kNttMax, p);
-        const uint64_t wi = host_pow(w, p - 2, p);
-        hipLaunchKernelGGL(k_twiddles, dim3(kNttMax / 2 / 256), dim3(256), 0, st, tw + (size_t)k * kNttMax,
-                           (uint32_t)w, (uint32_t)wi, k);
-      }
-    }
+    if (P.nmax) launch_twiddles((uint32_t*)(ws + P.off_tw), 3, st);
     // powers q^d by the chain
     std::vector<int> tab_len(t->n_table, 0);
     for (const auto& c : t->chain) {

@@ -72,3 +72,58 @@ def test_bigint_errors(dev):
         fpe.evaluate(t, [torch.zeros(4, dtype=torch.float64, device=dev)])
     got = fpe.eval_bigint(t, x).cpu().numpy()   # p(0) = 3
     assert got[0, 0] == 3 and not got[0, 1:].any()
+
+
+def run_point(exps, coeffs, scheme, x, lx, dev):
+    t = fpe.Tree(np.asarray(exps, dtype=np.int32).reshape(-1, 1), np.asarray(coeffs, dtype=np.uint64), scheme,
+                 fpe.BIGINT).upload(dev)
+    xl = torch.from_numpy(np.array(bigint.to_limbs(x, lx), dtype=np.int32)).to(dev)
+    out = fpe.eval_bigpoint(t, xl)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+def check_point(got, exps, coeffs, x):
+    terms = [((int(e),), int(c)) for e, c in zip(exps, coeffs)]
+    assert np.all((got >= 0) & (got < 1 << 16))
+    assert bigint.from_limbs(got.astype(np.int64) & 0xFFFF) == bigint.eval_int(terms, x)
+
+
+@pytest.mark.parametrize("scheme", ["horner", "estrin", "balanced", "balanced_floor"])
+def test_bigpoint_one_large_point_exact(dev, scheme):
+    """One polynomial at one big point (the Benchmarks section's setting):
+    dense and sparse, term counts at and just past powers of two, points of
+    1 to 512 limbs (products by transforms above 64 limbs per operand, up to
+    2^14 limbs),
+    64-bit coefficients including 2^64 - 1; every limb exact."""
+    g = np.random.default_rng([13075655, 7, 50])
+    for n, lx, sparse in [(1, 1, False), (7, 3, False), (63, 8, True), (64, 40, False), (65, 40, False),
+                          (128, 64, False), (129, 64, True), (300, 20, True), (24, 512, False)]:
+        say(f"bigpoint {scheme}: degree {n}, {lx} limbs, sparse={sparse}")
+        exps = np.arange(n + 1)
+        if sparse:
+            exps = np.sort(np.concatenate([g.choice(n, n // 3, replace=False), [n]]))
+            exps = np.unique(exps)
+        coeffs = g.integers(1, 2 ** 63, len(exps), dtype=np.uint64) * np.uint64(2) + np.uint64(1)
+        coeffs[-1] = np.uint64(2 ** 64 - 1)
+        x = int.from_bytes(g.bytes(2 * lx), "little") | (1 << (16 * lx - 1))
+        check_point(run_point(exps, coeffs, scheme, x, lx, dev), exps, coeffs, x)
+
+
+def test_bigpoint_special_points_and_errors(dev):
+    say("bigpoint: x = 0, 1, 2^16 - 1; errors")
+    exps, coeffs = np.arange(33), np.full(33, 2 ** 64 - 1, dtype=np.uint64)
+    for x, lx in [(0, 1), (1, 1), ((1 << 16) - 1, 1), (1 << 100, 8)]:
+        check_point(run_point(exps, coeffs, "balanced", x, lx, dev), exps, coeffs, x)
+    # p without a constant term: the root carries its own power
+    check_point(run_point([5, 9, 30], [3, 1, 7], "estrin", 12345678901234567, 4, dev), [5, 9, 30], [3, 1, 7],
+                12345678901234567)
+    t = fpe.Tree(np.arange(5, dtype=np.int32).reshape(-1, 1), np.ones(5), "horner", fpe.F64).upload(dev)
+    with pytest.raises(fpe.FpeError):
+        fpe.eval_bigpoint(t, torch.zeros(4, dtype=torch.int32, device=dev))
+    # a product beyond the largest transform is refused before any launch
+    t = fpe.Tree(np.arange(41, dtype=np.int32).reshape(-1, 1), np.ones(41, dtype=np.uint64), "horner",
+                 fpe.BIGINT).upload(dev)
+    with pytest.raises(fpe.FpeError) as e:
+        fpe.eval_bigpoint(t, torch.ones(1024, dtype=torch.int32, device=dev))
+    assert "2^14" in str(e.value)
