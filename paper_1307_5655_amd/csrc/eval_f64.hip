@@ -36,6 +36,8 @@ void launch_f64(const KernelLaunch& L, double* out) {
   const bool d2 = L.tr.depth <= 2, d6 = L.tr.depth <= 6, d8 = L.tr.depth <= 8;
   if (L.offt) {
     if (d8) go<8, 1, true>(L, out); else go<kMaxDepth, 1, true>(L, out);
+  } else if (L.ppl >= 8 && d2) {
+    go<2, 8, false>(L, out);
   } else if (L.ppl >= 4 && d2) {
     go<2, 4, false>(L, out);
   } else if (L.ppl >= 4 && d6) {

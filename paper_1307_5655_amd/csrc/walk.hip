@@ -23,14 +23,17 @@ namespace {
 // and trees with on-the-fly powers use the one-point kernels.
 int pick_ppl(const fpe_tree* t, const fpe_eval_opts* opts) {
   if (t->n_offtable > 0 || t->n_table > kTableCapMulti || t->domain == FPE_IVAL) return 1;
-  // Default: 4 points per lane for FP64, 2 otherwise (measured best on
-  // MI355X for both chain-like and deep walks once the power table lives in
-  // private memory); walks deeper than 8 hold twice the accumulators and take
-  // half as many points.
-  int p = opts && opts->points_per_lane > 0 ? opts->points_per_lane : (t->domain == FPE_F64 ? 4 : 2);
+  // Default: 4 points per lane for FP64 (8 for chain-like walks of depth
+  // <= 2, whose per-op cost is the wave-uniform dispatch: 4.7 -> 3.8 ms for
+  // Hörner at degree 5000 and 1e7 points, while the depth-6 walks gain nothing
+  // at 8 for the registers they lose), 2 otherwise (measured best on MI355X
+  // once the power table lives in private memory); walks deeper than 8 hold
+  // twice the accumulators and take half as many points.
+  const int dflt = t->domain != FPE_F64 ? 2 : t->depth <= 2 ? 8 : 4;
+  int p = opts && opts->points_per_lane > 0 ? opts->points_per_lane : dflt;
   if (t->depth > 8) p = std::min(p, t->domain == FPE_F64 ? 2 : 1);
   if (t->domain != FPE_F64) p = std::min(p, 2);
-  return p >= 4 ? 4 : p >= 2 ? 2 : 1;
+  return p >= 8 ? 8 : p >= 4 ? 4 : p >= 2 ? 2 : 1;
 }
 
 }  // namespace
