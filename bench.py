@@ -869,15 +869,14 @@ def main():
         "bigint_256bit_points": big,
         "bigint_one_512bit_point": bigpoint,
     }
+    # no child process is ever started; the device buffers of the phases are
+    # released before the line is printed, so the process ends right after it
+    import gc
+    gc.collect()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
     print(json.dumps(out), flush=True)
 
 
 if __name__ == "__main__":
     main()
-    # End the process as soon as the line is out: no child process is ever
-    # started, and the interpreter's and the GPU runtime's teardown of the
-    # many GB of device buffers is skipped rather than left running after
-    # the result.
-    sys.stdout.flush()
-    sys.stderr.flush()
-    os._exit(0)
