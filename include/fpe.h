@@ -252,10 +252,21 @@ size_t fpe_compose_workspace_bytes(const fpe_tree* t, int32_t dq);
  *                           exactly by number-theoretic transforms modulo three
  *                           primes below 2^31 and Garner's recombination
  *                           (subquadratic products, up to 2^14 coefficients)
- *   FPE_PRODUCT_AUTO        FUSED when deg_p * dq + 1 <= 4096, else NTT
+ *   FPE_PRODUCT_MFMA        the tree walked level by level (the nodes of one
+ *                           height, for all instances, in one launch; Section 1's
+ *                           definition u(N) = c(N) + sum_C u(C) q^d(C)), each
+ *                           product of at least 256 output coefficients an exact
+ *                           integer matrix product on the matrix cores (balanced
+ *                           8-bit digits of the centred residues, Toeplitz
+ *                           blocks, 32x32x32 int8 MFMA), smaller ones on a
+ *                           schoolbook kernel; nodes of up to 4096 output
+ *                           coefficients on the matrix cores, longer ones schoolbook
+ *   FPE_PRODUCT_AUTO        deg_p * dq + 1 <= 4096: MFMA when the level walk
+ *                           takes at most 64 launches (divide-and-conquer
+ *                           trees), else FUSED; beyond 4096: NTT
  * All give the same residues. */
 typedef enum { FPE_PRODUCT_AUTO = 0, FPE_PRODUCT_FUSED = 1, FPE_PRODUCT_SCHOOLBOOK = 2,
-               FPE_PRODUCT_NTT = 3 } fpe_product;
+               FPE_PRODUCT_NTT = 3, FPE_PRODUCT_MFMA = 4 } fpe_product;
 size_t fpe_compose_ex_workspace_bytes(const fpe_tree* t, int32_t dq, int32_t product);
 /* fpe_compose with a chosen product method (fpe_compose is FPE_PRODUCT_AUTO).
  * Errors: as fpe_compose; FPE_EUNSUPPORTED if a transform would exceed 2^14

@@ -382,8 +382,9 @@ def eval_bigint(tree: Tree, x, lout=None, out=None, workspace=None, stream=None,
     return out
 
 
-PRODUCT_AUTO, PRODUCT_FUSED, PRODUCT_SCHOOLBOOK, PRODUCT_NTT = 0, 1, 2, 3
-PRODUCTS = {"auto": PRODUCT_AUTO, "fused": PRODUCT_FUSED, "schoolbook": PRODUCT_SCHOOLBOOK, "ntt": PRODUCT_NTT}
+PRODUCT_AUTO, PRODUCT_FUSED, PRODUCT_SCHOOLBOOK, PRODUCT_NTT, PRODUCT_MFMA = 0, 1, 2, 3, 4
+PRODUCTS = {"auto": PRODUCT_AUTO, "fused": PRODUCT_FUSED, "schoolbook": PRODUCT_SCHOOLBOOK, "ntt": PRODUCT_NTT,
+            "mfma": PRODUCT_MFMA}
 
 
 def eval_bigpoint(tree: Tree, x, out=None, workspace=None, stream=None, check=True):

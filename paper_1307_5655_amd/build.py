@@ -12,7 +12,8 @@ LIB = os.path.join(HERE, "libfpe.so")
 PROBE_LIB = os.path.join(HERE, "libfpe_probe.so")
 PROBE_SOURCES = ["probes.hip"]
 SOURCES = ["compile.cpp", "api.cpp", "walk.hip", "eval_f64.hip", "eval_m61.hip", "eval_df32.hip", "eval_iv.hip", "bigint.hip",
-           "serve_kernels.hip", "compose.hip", "ntt.hip", "bigpoint.hip", "server.cpp"]
+           "serve_kernels.hip", "compose.hip", "ntt.hip", "compose_mfma.hip", "bigpoint.hip",
+           "server.cpp"]
 EXTRA_SOURCES = []
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -92,6 +92,7 @@ fpe_status fpe_compile(int32_t nvars, int64_t nterms, const int32_t* exps, const
 void fpe_tree_free(fpe_tree* t) {
   if (!t) return;
   bigpoint_forget(t);
+  compose_levels_forget(t);
   delete t;
 }
 
@@ -424,7 +425,7 @@ fpe_status fpe_compose_ex(const fpe_tree* t, const uint32_t* q, int32_t dq, uint
   if (t->domain != FPE_MODP || t->modulus != kP31 || t->nvars != 1)
     return fail(FPE_EINVAL, "composition needs a univariate tree compiled mod 2^31-1");
   if (dq < 1) return fail(FPE_EINVAL, "deg q must be >= 1");
-  if (product < FPE_PRODUCT_AUTO || product > FPE_PRODUCT_NTT) return fail(FPE_EINVAL, "unknown product method");
+  if (product < FPE_PRODUCT_AUTO || product > FPE_PRODUCT_MFMA) return fail(FPE_EINVAL, "unknown product method");
   return launch_compose_ex(t, q, dq, out, workspace, workspace_bytes, product, stream);
 }
 

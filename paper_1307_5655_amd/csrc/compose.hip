@@ -268,16 +268,23 @@ fpe_status launch_compose_fused(const fpe_tree* t, const uint32_t* q, int32_t dq
   return FPE_OK;
 }
 
-// The product method of a composition: the fused walk (one wavefront per
-// instance, all products schoolbook) for outputs that fit its design, and
-// the op-by-op walk with transform products beyond.
+// The product method of a composition: for outputs that fit one node's four
+// matrix tiles, the level walk with matrix-core products when the tree has
+// few levels (divide-and-conquer schemes), else the fused walk (one
+// wavefront per instance, all products schoolbook); beyond, the op-by-op
+// walk with transform products.
 constexpr int64_t kFusedMaxOut = 4096;
 constexpr int32_t kNttMinOperand = 64;
+constexpr int64_t kLevelsMaxLaunches = 64;
 int32_t compose_method(const fpe_tree* t, int32_t dq, int32_t product) {
   if (product != FPE_PRODUCT_AUTO) return product;
   int32_t dp = 0;
   for (size_t i = 0; i < t->nodes.size(); ++i) dp = std::max(dp, t->exps[i * t->nvars]);
-  return (int64_t)dp * dq + 1 <= kFusedMaxOut ? FPE_PRODUCT_FUSED : FPE_PRODUCT_NTT;
+  if ((int64_t)dp * dq + 1 > kFusedMaxOut) return FPE_PRODUCT_NTT;
+  int64_t launches = 0;
+  if (t->n_offtable == 0 && compose_levels_ok(t, dq, &launches) && launches <= kLevelsMaxLaunches)
+    return FPE_PRODUCT_MFMA;
+  return FPE_PRODUCT_FUSED;
 }
 
 size_t compose_workspace_bytes_ex(const fpe_tree* t, int32_t dq, int32_t product) {
@@ -286,6 +293,7 @@ size_t compose_workspace_bytes_ex(const fpe_tree* t, int32_t dq, int32_t product
     case FPE_PRODUCT_FUSED: return compose_fused_workspace_bytes(t, dq);
     case FPE_PRODUCT_SCHOOLBOOK: return compose_ops_workspace_bytes(t, dq, 1 << 30);
     case FPE_PRODUCT_NTT: return compose_ops_workspace_bytes(t, dq, kNttMinOperand);
+    case FPE_PRODUCT_MFMA: return compose_levels_workspace_bytes(t, dq);
   }
   return 0;
 }
@@ -299,6 +307,7 @@ fpe_status launch_compose_ex(const fpe_tree* t, const uint32_t* q, int32_t dq, u
     case FPE_PRODUCT_FUSED: return launch_compose_fused(t, q, dq, out, ws, ws_bytes, stream);
     case FPE_PRODUCT_SCHOOLBOOK: return launch_compose_ops(t, q, dq, out, ws, ws_bytes, 1 << 30, stream);
     case FPE_PRODUCT_NTT: return launch_compose_ops(t, q, dq, out, ws, ws_bytes, kNttMinOperand, stream);
+    case FPE_PRODUCT_MFMA: return launch_compose_levels(t, q, dq, out, ws, ws_bytes, stream);
   }
   return fail(FPE_EINVAL, "unknown product method");
 }

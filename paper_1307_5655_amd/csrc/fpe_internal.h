@@ -240,6 +240,13 @@ fpe_status launch_compose_ex(const fpe_tree* t, const uint32_t* q, int32_t dq, u
 size_t compose_ops_workspace_bytes(const fpe_tree* t, int32_t dq, int32_t ntt_min);
 fpe_status launch_compose_ops(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* ws,
                               size_t ws_bytes, int32_t ntt_min, void* stream);
+// the composition walk level by level, large products on the matrix cores
+// (compose_mfma.hip); its schedule is cached per tree and dq
+size_t compose_levels_workspace_bytes(const fpe_tree* t, int32_t dq);
+bool compose_levels_ok(const fpe_tree* t, int32_t dq, int64_t* launches);
+fpe_status launch_compose_levels(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_t* out, void* ws,
+                                 size_t ws_bytes, void* stream);
+void compose_levels_forget(const fpe_tree* t);
 fpe_status launch_bigint(const fpe_tree* t, const uint32_t* x, int32_t lx, int64_t batch, uint32_t* out,
                          int32_t lout, void* ws, size_t ws_bytes, void* stream);
 size_t bigint_workspace_bytes(const fpe_tree* t, int32_t lout, int64_t batch);

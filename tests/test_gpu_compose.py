@@ -95,19 +95,21 @@ def gpu_compose_method(P, Q, scheme, dev, product):
 
 @pytest.mark.parametrize("scheme", ["balanced", "estrin", "horner", "balanced_floor"])
 def test_compose_product_methods_agree_exactly(dev, scheme):
-    """The fused walk, the op-by-op walk with schoolbook products and the
-    op-by-op walk with transform products give the same residues, equal to
-    the oracle's expansion (sparse p with a zero constant term included)."""
+    """The fused walk, the op-by-op walk with schoolbook products, the
+    op-by-op walk with transform products and the level walk with matrix-core
+    products give the same residues, equal to the oracle's expansion (sparse
+    p with a zero constant term included)."""
     say(f"compose product methods {scheme}")
     g = np.random.default_rng([13075655, 930])
-    for b, dp, dq in [(37, 255, 15), (9, 130, 7), (5, 64, 63), (4, 300, 1)]:
+    for b, dp, dq in [(37, 255, 15), (9, 130, 7), (5, 64, 63), (4, 300, 1), (3, 273, 15)]:
         P = g.integers(0, P31, size=(b, dp + 1), dtype=np.uint32)
         P[:, 0] = 0
         P[:, g.choice(dp, dp // 10, replace=False)] = 0
         Q = g.integers(0, P31, size=(b, dq + 1), dtype=np.uint32)
-        got = {m: gpu_compose_method(P, Q, scheme, dev, m) for m in ("fused", "schoolbook", "ntt")}
+        got = {m: gpu_compose_method(P, Q, scheme, dev, m) for m in ("fused", "schoolbook", "ntt", "mfma")}
         assert np.array_equal(got["fused"], got["ntt"]), (b, dp, dq)
         assert np.array_equal(got["fused"], got["schoolbook"]), (b, dp, dq)
+        assert np.array_equal(got["fused"], got["mfma"]), (b, dp, dq)
         want = native.compose_modp(P[:3], Q[:3], P31)
         assert np.array_equal(got["ntt"][:3], want), (b, dp, dq)
 
@@ -130,3 +132,58 @@ def test_compose_ntt_beyond_the_fused_walk(dev):
         t = int(rng.integers(2, P31 - 1))
         assert ocomp.horner_at(res["balanced"][b].tolist(), t, P31) == \
             ocomp.compose_at(P[b].tolist(), Q[b].tolist(), t, P31), b
+
+
+def test_compose_mfma_digit_extremes_and_shapes(dev):
+    """The level walk's matrix-core products on residues at the ends of the
+    balanced-digit range (0, 1, (p - 1) / 2, (p + 1) / 2, p - 2, p - 1: every
+    digit at -128 or 127 somewhere), a constant p, a single term c x^k (a
+    leaf root with its own power), outputs ending exactly on a tile (4096 =
+    273 * 15 + 1) and one past it with the long node on the schoolbook
+    kernel, each bit-exact against the oracle's expansion."""
+    say("compose mfma: digit extremes, constant and monomial p, tile edges")
+    g = np.random.default_rng([13075655, 932])
+    ext = np.array([0, 1, (P31 - 1) // 2, (P31 + 1) // 2, P31 - 2, P31 - 1, 0x7F7F7F7F, 0x80808080 % P31],
+                   dtype=np.uint32)
+    for b, dp, dq in [(4, 255, 15), (3, 273, 15), (2, 70, 63)]:
+        P = ext[g.integers(0, len(ext), size=(b, dp + 1))]
+        Q = ext[g.integers(0, len(ext), size=(b, dq + 1))]
+        Q[:, dq] = P31 - 1
+        P[:, dp] = P31 - 1
+        for scheme in ("balanced", "estrin"):
+            got = gpu_compose_method(P, Q, scheme, dev, "mfma")
+            assert np.array_equal(got, native.compose_modp(P, Q, P31)), (b, dp, dq, scheme)
+    # p = c (constant) and p = c x^k
+    Q = g.integers(0, P31, size=(2, 8), dtype=np.uint32)
+    t = fpe.Tree(np.zeros((1, 1), np.int32), np.array([[12345], [678]], np.uint64), "balanced", fpe.MODP,
+                 P31).upload(dev)
+    out = fpe.compose(t, torch.from_numpy(Q.astype(np.int32)).to(dev), product="mfma")
+    torch.cuda.synchronize()
+    assert out.cpu().numpy().view(np.uint32).tolist() == [[12345], [678]]
+    t = fpe.Tree(np.array([[9]], np.int32), np.array([[5], [P31 - 1]], np.uint64), "estrin", fpe.MODP,
+                 P31).upload(dev)
+    out = fpe.compose(t, torch.from_numpy(Q.astype(np.int32)).to(dev), product="mfma")
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    for b, c in enumerate([5, P31 - 1]):
+        pk = [0] * 9 + [c]
+        assert got[b].tolist() == ocomp.compose(pk, Q[b].tolist(), P31), b
+    # past four tiles: the root's products on the schoolbook kernel
+    P = g.integers(0, P31, size=(2, 301), dtype=np.uint32)
+    Q = g.integers(0, P31, size=(2, 16), dtype=np.uint32)
+    got = gpu_compose_method(P, Q, "balanced", dev, "mfma")
+    assert np.array_equal(got, native.compose_modp(P, Q, P31))
+
+
+def test_compose_mfma_full_size_matches_fused(dev):
+    """4096 x (255 o 15), the composition benchmark: the level walk equals the
+    fused walk bit for bit on every instance (Estrin and balanced), and the
+    oracle's expansion on a sample."""
+    say("compose 4096 x (255 o 15): mfma vs fused")
+    inp = fpe_inputs.compose_batch()
+    for scheme in ("estrin", "balanced"):
+        a = gpu_compose_method(inp.p, inp.q, scheme, dev, "mfma")
+        b = gpu_compose_method(inp.p, inp.q, scheme, dev, "fused")
+        assert np.array_equal(a, b), scheme
+    idx = [0, 1, 4095]
+    assert np.array_equal(a[idx], native.compose_modp(inp.p[idx], inp.q[idx], P31))
