@@ -31,7 +31,9 @@
 // and each value's factor sits in its own blocks of the h operand, so the
 // small products of the lower levels fill the tiles as well as the large ones
 // at the top.  Values beyond four tiles (4096 coefficients) or the exactness
-// bound go to a VALU schoolbook kernel (a thread per output coefficient).
+// bound, and the short values of the lowest levels (at most 64
+// coefficients: too little work to pay for a workgroup's staging) go to a
+// VALU schoolbook kernel (a thread per output coefficient).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -48,11 +50,14 @@ typedef int8_t i8x16 __attribute__((ext_vector_type(16)));
 typedef int32_t i32x16 __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
-constexpr int kMaxTiles = 4;             // tiles of one workgroup: one wavefront each
+constexpr int kMaxTiles = 4;             // tiles (32 x 32 outputs) of one workgroup
+constexpr int kWaves = 4;                // wavefronts of one workgroup
 constexpr int kCols = 32 * kMaxTiles;    // output blocks of 32 coefficients per workgroup
+constexpr int kObufTile = 32 * 33;       // 64-bit sums of one tile in LDS (rows padded to 33)
+constexpr int64_t kPipeMinBlocks = 16;   // shares of at least this many blocks use two operand sets
+constexpr int32_t kValuMaxOut = 64;      // values this short go to the VALU kernel (latency-bound either way)
 constexpr int kGroups = 7;               // digit pairs (s, a) grouped by s + a
 constexpr int kMaxLaunchY = 65535;
-constexpr size_t kMaxLds = 64 * 1024;
 constexpr int64_t kExactLimit = int64_t(1) << 15;   // summed min(lt, lh) over a value's products
 
 // Where a polynomial lives: the instance's arena, the caller's q or output,
@@ -138,36 +143,43 @@ struct GParent {   // a value of a group
 struct GRound {    // the products of a group by one power t
   CRef t;
   int32_t lt;
-  int32_t e_begin, e_end;   // entries (the factors h)
   int32_t hblocks;          // 32-byte blocks of each h digit plane (block 0: zeros)
   int32_t b_begin;          // hblocks records: the entry of each block (-1: zeros)
-  int32_t col_begin;        // kCols column records
-  int32_t r_lo[kMaxTiles], r_hi[kMaxTiles];   // blocks r of t that reach each tile
+  int32_t pe_begin;         // one record per value of the group: its entry in this round (-1: none)
+  int32_t tbase, ntp;       // LDS byte offset of the 4 t digit planes, bytes per plane
+  int32_t hbase;            // LDS byte offset of the 4 h digit planes (32 hblocks bytes each)
+  int32_t pad;
 };
 struct GEntry {    // one factor: its blocks start at block hblk (>= 1) of the h planes
   CRef h;
   int32_t lh;
   int32_t hblk;
 };
-struct GCol {      // column m in a round: h block hblk + (m - base - r), if m - base - r < J
-  int32_t hblk, base, J;
-};
 struct GOwn {      // column m of a group: its value (-1: none) and the value's first column
   int32_t parent, base;
 };
+struct GSeg {      // blocks r in [r_lo, r_hi] of one round for one tile
+  int32_t tile, round, r_lo, r_hi;
+};
+// A group's records are contiguous in each list; the kernel copies them to
+// LDS (at mbase) before anything else.
 struct GGroup {
-  int32_t p_begin, p_end, rd_begin, rd_end;
+  int32_t p_begin, p_end, rd_begin, rd_end, e_begin, e_end, b_begin, b_end, pe_begin, pe_end;
   int32_t own_begin;
   int32_t ntiles;
+  int32_t obase;                               // LDS byte offset of the tiles' sums
+  int32_t mbase;                               // LDS byte offset of the copied records
+  int32_t seg_begin[kWaves], seg_end[kWaves];  // the segments of each wavefront
 };
 struct GLists {
   const GGroup* groups;
   const GParent* pars;
   const GRound* rounds;
   const GEntry* ents;
-  const GCol* cols;
   const GOwn* own;
   const int32_t* bent;
+  const int32_t* pent;
+  const GSeg* segs;
 };
 
 // The four balanced digits of the centred residue of v (v < p), byte s
@@ -187,122 +199,231 @@ __device__ __forceinline__ void transpose4(const uint32_t w[4], uint32_t d[4]) {
   d[3] = (hi01 >> 16) | (hi23 & 0xFFFF0000u);
 }
 
-// LDS: 16 planes of the Toeplitz operand (digit s, byte shift e, at
-// (4 s + e) * ntp), then 4 digit planes of h (hp bytes each).  Plane (s, e)
-// holds byte y = digit s of trev[y + e], where trev[x] = t[X0 - x] (zero
-// outside t), so that a lane whose read starts at a byte = e mod 4 reads four
-// aligned words; ntp = 64 mod 256, so the four copies fall in disjoint LDS
-// banks.  An h plane holds 32-byte blocks (block 0 zeros, read by the lanes
-// whose block falls outside their factor) as two halves: bytes 0..15 of every
-// block, then bytes 16..31, so that the 16-byte reads of consecutive lanes
-// are consecutive.  Three wavefronts per SIMD (the register budget of the
-// accumulators plus one operand set).
-__global__ __launch_bounds__(256, 3) void k_cm_mfma(GLists Ls, CBases B, int32_t ntp, int32_t hp) {
+// The 16 Toeplitz bytes of this lane for one digit plane, from the five
+// aligned words d (its window starts e bytes into d[0]).
+__device__ __forceinline__ i8x16 toeplitz_bytes(const uint32_t d[5], uint32_t e) {
+  const u32x4 v = {__builtin_amdgcn_alignbyte(d[1], d[0], e), __builtin_amdgcn_alignbyte(d[2], d[1], e),
+                   __builtin_amdgcn_alignbyte(d[3], d[2], e), __builtin_amdgcn_alignbyte(d[4], d[3], e)};
+  return __builtin_bit_cast(i8x16, v);
+}
+
+__device__ __forceinline__ void copy_words(void* dst, const void* src, int bytes) {
+  for (int i = threadIdx.x; i < bytes / 4; i += blockDim.x) ((uint32_t*)dst)[i] = ((const uint32_t*)src)[i];
+}
+__host__ __device__ constexpr int al16(int v) { return (v + 15) & ~15; }
+
+// A workgroup copies its group's records to LDS, stages every round's
+// operands in LDS at once, then each wavefront runs its own list of segments
+// (the host splits the group's (tile, round, block) work evenly over the
+// four wavefronts), adding the partial sums of each tile it touched into the
+// tiles' 64-bit sums in LDS.
+//
+// LDS per round: 4 digit planes of the Toeplitz operand, where byte y of
+// plane s is digit s of trev[y] = t[X0 - y] (zero outside t): the lane's 16
+// bytes for block r start at byte s0 - 32 r (s0 = X0 - u + 16 hh) and are
+// cut from five aligned words; then 4 digit planes of h in 32-byte blocks
+// (block 0 zeros, read by the lanes whose block falls outside their factor),
+// each plane as two halves (bytes 0..15 of every block, then 16..31) so the
+// 16-byte reads of consecutive lanes are consecutive.  The tiles' sums are
+// 32 x 33 words per tile (row-major, padded), residues < p added by at most
+// four wavefronts.  kPipe: two operand sets, the next block's loads in
+// flight during the current block's products (two wavefronts per SIMD);
+// otherwise one set and three wavefronts per SIMD.
+template <bool kPipe>
+__global__ __launch_bounds__(256, kPipe ? 2 : 3) void k_cm_mfma(GLists Ls, CBases B) {
   extern __shared__ __align__(16) uint8_t lds[];
-  uint8_t* tpl = lds;
-  uint8_t* hpl = lds + 16 * ntp;
   const GGroup G = Ls.groups[blockIdx.y];
   const int64_t inst = blockIdx.x;
-  const int tid = threadIdx.x, lane = tid & 63, nthr = blockDim.x;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int u = lane & 31, hh = lane >> 5;
-  const int m = 32 * wave + u;   // this lane's output block (column) in the group
-  i32x16 acc[kGroups];
-#pragma unroll
-  for (int g = 0; g < kGroups; ++g) acc[g] = i32x16{};
+  const int npar = G.p_end - G.p_begin;
+  // the group's records
+  uint8_t* mp = lds + G.mbase;
+  GRound* Rl = (GRound*)mp;
+  mp += al16((G.rd_end - G.rd_begin) * (int)sizeof(GRound));
+  GEntry* El = (GEntry*)mp;
+  mp += al16((G.e_end - G.e_begin) * (int)sizeof(GEntry));
+  GParent* Pl = (GParent*)mp;
+  mp += al16(npar * (int)sizeof(GParent));
+  GOwn* Ol = (GOwn*)mp;
+  mp += al16(kCols * (int)sizeof(GOwn));
+  int32_t* Bl = (int32_t*)mp;
+  mp += al16((G.b_end - G.b_begin) * 4);
+  int32_t* PEl = (int32_t*)mp;
+  mp += al16((G.pe_end - G.pe_begin) * 4);
+  uint32_t* Cl = (uint32_t*)mp;
+  copy_words(Rl, Ls.rounds + G.rd_begin, (G.rd_end - G.rd_begin) * (int)sizeof(GRound));
+  copy_words(El, Ls.ents + G.e_begin, (G.e_end - G.e_begin) * (int)sizeof(GEntry));
+  copy_words(Pl, Ls.pars + G.p_begin, npar * (int)sizeof(GParent));
+  copy_words(Ol, Ls.own + G.own_begin, kCols * (int)sizeof(GOwn));
+  copy_words(Bl, Ls.bent + G.b_begin, (G.b_end - G.b_begin) * 4);
+  copy_words(PEl, Ls.pent + G.pe_begin, (G.pe_end - G.pe_begin) * 4);
+  for (int j = tid; j < npar; j += blockDim.x) {
+    const int cn = Ls.pars[G.p_begin + j].coef_node;
+    Cl[j] = cn >= 0 ? B.coef[inst * B.n_nodes + cn] : 0u;
+  }
+  uint64_t* obuf = (uint64_t*)(lds + G.obase);
+  for (int i = tid; i < G.ntiles * kObufTile; i += blockDim.x) obuf[i] = 0u;
+  __syncthreads();
 
-  for (int rd = G.rd_begin; rd < G.rd_end; ++rd) {
-    const GRound R = Ls.rounds[rd];
+  for (int rl = 0; rl < G.rd_end - G.rd_begin; ++rl) {
+    const GRound& R = Rl[rl];
     const uint32_t* tv = cptr(B, R.t, inst);
-    const int rmax = (R.lt + 30) >> 5;   // blocks r with a nonzero t[32 r + u - k]
-    const int X0 = 32 * rmax + 31;
-    const int ntw = ((X0 + 31) >> 2) + 1;
-    __syncthreads();   // the previous round's operands are no longer read
-    for (int w = tid; w < ntw; w += nthr) {
-      uint32_t pk[8], lo[4], hi[4];
+    const int lt = R.lt;
+    const int X0 = 32 * ((lt + 30) >> 5) + 31;
+    uint32_t* tp = (uint32_t*)(lds + R.tbase);
+    const int ntw = R.ntp >> 2;
+    for (int w = tid; w < ntw; w += blockDim.x) {
+      uint32_t pk[4], d[4];
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
+      for (int b = 0; b < 4; ++b) {
         const int i = X0 - 4 * w - b;
-        pk[b] = digit_word((i >= 0 && i < R.lt) ? tv[i] : 0u);
+        pk[b] = digit_word((i >= 0 && i < lt) ? tv[i] : 0u);
       }
-      transpose4(pk, lo);
-      transpose4(pk + 4, hi);
+      transpose4(pk, d);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        ((uint32_t*)(tpl + (4 * s + 0) * ntp))[w] = lo[s];
-        ((uint32_t*)(tpl + (4 * s + 1) * ntp))[w] = __builtin_amdgcn_alignbyte(hi[s], lo[s], 1);
-        ((uint32_t*)(tpl + (4 * s + 2) * ntp))[w] = __builtin_amdgcn_alignbyte(hi[s], lo[s], 2);
-        ((uint32_t*)(tpl + (4 * s + 3) * ntp))[w] = __builtin_amdgcn_alignbyte(hi[s], lo[s], 3);
-      }
+      for (int s = 0; s < 4; ++s) tp[s * ntw + w] = d[s];
     }
-    const int hwords = 8 * R.hblocks;
-    for (int W = tid; W < hwords; W += nthr) {
+    uint32_t* hp = (uint32_t*)(lds + R.hbase);
+    const int hb = R.hblocks, hwords = 8 * hb;
+    for (int W = tid; W < hwords; W += blockDim.x) {
       uint32_t pk[4] = {0u, 0u, 0u, 0u}, d[4];
       const int blk = W >> 3, wi = W & 7;
-      const int ei = Ls.bent[R.b_begin + blk];
+      const int ei = Bl[R.b_begin - G.b_begin + blk];
       if (ei >= 0) {
-        const GEntry E = Ls.ents[ei];
+        const GEntry& E = El[ei - G.e_begin];
         const uint32_t* hv = cptr(B, E.h, inst);
         const int i0 = 32 * (blk - E.hblk) + 4 * wi;
 #pragma unroll
         for (int b = 0; b < 4; ++b) pk[b] = digit_word(i0 + b < E.lh ? hv[i0 + b] : 0u);
       }
       transpose4(pk, d);
-      const int dst = (wi >> 2) * 4 * R.hblocks + 4 * blk + (wi & 3);
+      const int dst = (wi >> 2) * 4 * hb + 4 * blk + (wi & 3);
 #pragma unroll
-      for (int s = 0; s < 4; ++s) ((uint32_t*)(hpl + s * hp))[dst] = d[s];
+      for (int s = 0; s < 4; ++s) hp[s * hwords + dst] = d[s];
     }
-    __syncthreads();
-    if (wave < G.ntiles) {
-      const int r_lo = R.r_lo[wave], r_hi = R.r_hi[wave];
-      if (r_lo <= r_hi) {
-        const GCol c = Ls.cols[R.col_begin + m];
-        // this lane's row u of the Toeplitz operand holds k = 16 hh + j (byte
-        // j): t[32 r + u - k] = trev[s0 - 32 r + j]
-        const int s0 = X0 - u + 16 * hh;
-        const int e = s0 & 3;
-        const uint8_t* ta = tpl + e * ntp + (s0 - e);
-        const int jb0 = m - c.base;
-        for (int r = r_lo; r <= r_hi; ++r) {
-          i8x16 A[4], H[4];
+  }
+  __syncthreads();
+
+  i32x16 acc[kGroups];
 #pragma unroll
-          for (int s = 0; s < 4; ++s) {
-            const uint32_t* p = (const uint32_t*)(ta + 4 * s * ntp - 32 * r);
-            const u32x4 v = {p[0], p[1], p[2], p[3]};
-            A[s] = __builtin_bit_cast(i8x16, v);
-          }
-          const int jb = jb0 - r;
-          const int hoff = 16 * (((unsigned)jb < (unsigned)c.J ? c.hblk + jb : 0) + hh * R.hblocks);
+  for (int g = 0; g < kGroups; ++g) acc[g] = i32x16{};
+  auto flush = [&](int tile) {
+    constexpr int kShift[kGroups] = {0, 8, 16, 24, 1, 9, 17};   // 8 g mod 31
 #pragma unroll
-          for (int s = 0; s < 4; ++s) H[s] = __builtin_bit_cast(i8x16, *(const u32x4*)(hpl + s * hp + hoff));
+    for (int rr = 0; rr < 16; ++rr) {
+      const int row = 8 * (rr >> 2) + 4 * hh + (rr & 3);
+      int64_t v = 0;
 #pragma unroll
-          for (int a = 0; a < 4; ++a)
+      for (int g = 0; g < kGroups; ++g) v += (int64_t)acc[g][rr] * (int64_t(1) << kShift[g]);
+      // |v| < 2^31 (2^24 + 2^17 + 2^16 + 2^9 + 2^8 + 3) < 2^56: add 2^27 p
+      atomicAdd((unsigned long long*)&obuf[tile * kObufTile + row * 33 + u],
+                (unsigned long long)reduce31((uint64_t)(v + ((int64_t)kP31 << 27))));
+    }
 #pragma unroll
-            for (int s = 0; s < 4; ++s)
-              acc[a + s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], H[s], acc[a + s], 0, 0, 0);
+    for (int g = 0; g < kGroups; ++g) acc[g] = i32x16{};
+  };
+  int cur = -1;
+  for (int sg = G.seg_begin[wave]; sg < G.seg_end[wave]; ++sg) {
+    const GSeg S = Ls.segs[sg];
+    if (S.tile != cur) {
+      if (cur >= 0) flush(cur);
+      cur = S.tile;
+    }
+    const GRound& R = Rl[S.round - G.rd_begin];
+    // this lane's output block, its value's factor in this round
+    const int m = 32 * S.tile + u;
+    const GOwn o = Ol[m];
+    int hblk = 0, J = 0, jb0 = 0;
+    if (o.parent >= 0) {
+      const int ei = PEl[R.pe_begin - G.pe_begin + o.parent];
+      if (ei >= 0) {
+        hblk = El[ei - G.e_begin].hblk;
+        J = (El[ei - G.e_begin].lh + 31) >> 5;
+        jb0 = m - o.base;
+      }
+    }
+    // this lane's row u of the Toeplitz operand holds k = 16 hh + j (byte
+    // j): t[32 r + u - k] = trev[s0 - 32 r + j]
+    const int X0 = 32 * ((R.lt + 30) >> 5) + 31;
+    const int s0 = X0 - u + 16 * hh;
+    const uint32_t e = s0 & 3;
+    const int ntw = R.ntp >> 2;
+    const uint32_t* tp = (const uint32_t*)(lds + R.tbase) + (s0 >> 2);
+    const uint8_t* hp = lds + R.hbase + 16 * hh * R.hblocks;
+    const int hpb = 32 * R.hblocks;
+    auto load = [&](int r, uint32_t (&d)[4][5], u32x4 (&h)[4]) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int k = 0; k < 5; ++k) d[s][k] = tp[s * ntw - 8 * r + k];
+      const int jb = jb0 - r;
+      const int off = 16 * ((unsigned)jb < (unsigned)J ? hblk + jb : 0);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) h[s] = *(const u32x4*)(hp + s * hpb + off);
+    };
+    auto mma = [&](const uint32_t (&d)[4][5], const u32x4 (&h)[4]) {
+      i8x16 A[4];
+#pragma unroll
+      for (int s = 0; s < 4; ++s) A[s] = toeplitz_bytes(d[s], e);
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int s = 0; s < 4; ++s)
+          acc[a + s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], __builtin_bit_cast(i8x16, h[s]), acc[a + s], 0,
+                                                              0, 0);
+    };
+    uint32_t d0[4][5];
+    u32x4 h0[4];
+    if constexpr (kPipe) {
+      uint32_t d1[4][5];
+      u32x4 h1[4];
+      int r = S.r_lo;
+      load(r, d0, h0);
+      for (; r + 1 <= S.r_hi; r += 2) {
+        load(r + 1, d1, h1);
+        mma(d0, h0);
+        if (r + 2 <= S.r_hi) load(r + 2, d0, h0);
+        mma(d1, h1);
+      }
+      if (r == S.r_hi) mma(d0, h0);
+    } else {
+      // one plane of the Toeplitz operand at a time: its words are loaded
+      // while the previous plane's products run
+      const int off0 = jb0;
+      for (int r = S.r_lo; r <= S.r_hi; ++r) {
+        const int jb = off0 - r;
+        const int off = 16 * ((unsigned)jb < (unsigned)J ? hblk + jb : 0);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) h0[s] = *(const u32x4*)(hp + s * hpb + off);
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          uint32_t w[5];
+#pragma unroll
+          for (int k = 0; k < 5; ++k) w[k] = tp[a * ntw - 8 * r + k];
+          const i8x16 A = toeplitz_bytes(w, e);
+#pragma unroll
+          for (int s = 0; s < 4; ++s)
+            acc[a + s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, __builtin_bit_cast(i8x16, h0[s]), acc[a + s], 0,
+                                                                0, 0);
         }
       }
     }
   }
-  if (wave < G.ntiles) {
-    const GOwn o = Ls.own[G.own_begin + m];
-    if (o.parent >= 0) {
-      const GParent P = Ls.pars[G.p_begin + o.parent];
-      uint32_t* out = optr(B, P.out, inst);
-      const uint64_t c0 = P.coef_node >= 0 ? B.coef[inst * B.n_nodes + P.coef_node] : 0u;
-      constexpr int kShift[kGroups] = {0, 8, 16, 24, 1, 9, 17};   // 8 g mod 31
-#pragma unroll
-      for (int rr = 0; rr < 16; ++rr) {
-        const int row = 8 * (rr >> 2) + 4 * hh + (rr & 3);
-        const int n = 32 * (m - o.base) + row;
-        int64_t v = 0;
-#pragma unroll
-        for (int g = 0; g < kGroups; ++g) v += (int64_t)acc[g][rr] * (int64_t(1) << kShift[g]);
-        // |v| < 2^31 (2^24 + 2^17 + 2^16 + 2^9 + 2^8 + 3) < 2^56: add 2^27 p
-        const uint64_t w = (uint64_t)(v + ((int64_t)kP31 << 27)) + (n == 0 ? c0 : 0u);
-        if (n < P.lout) out[n] = reduce31(w);
-      }
-    }
+  if (cur >= 0) flush(cur);
+  __syncthreads();
+  for (int idx = tid; idx < G.ntiles * 1024; idx += blockDim.x) {
+    const int tile = idx >> 10, col = (idx >> 5) & 31, row = idx & 31;
+    const int m = 32 * tile + col;
+    const GOwn o = Ol[m];
+    if (o.parent < 0) continue;
+    const GParent& P = Pl[o.parent];
+    const int n = 32 * (m - o.base) + row;
+    if (n >= P.lout) continue;
+    uint64_t v = obuf[tile * kObufTile + row * 33 + col];
+    if (n == 0) v += Cl[o.parent];
+    optr(B, P.out, inst)[n] = reduce31(v);
   }
 }
 
@@ -333,9 +454,9 @@ struct Value {     // out = c(coef_node) + sum of prods
 struct Launch {
   int32_t mfma;
   int32_t begin, end;   // groups (mfma) or VALU parents
-  int32_t waves;
-  int32_t ntp, hp;
+  int32_t lds;          // dynamic LDS bytes (mfma)
   int32_t max_lout;
+  int32_t pipe;         // the kernel with two operand sets (groups with long shares)
 };
 struct CSched {
   int32_t dq = 0;
@@ -343,24 +464,26 @@ struct CSched {
   std::vector<GParent> gpars;
   std::vector<GRound> rounds;
   std::vector<GEntry> ents;
-  std::vector<GCol> cols;
   std::vector<GOwn> own;
-  std::vector<int32_t> bent;
+  std::vector<int32_t> bent, pent;
+  std::vector<GSeg> segs;
   std::vector<CParent> vpars;
   std::vector<CChild> vch;
   std::vector<Launch> launches;
   int64_t arena_words = 0, out_len = 0, lmax = 0;
-  size_t off[9] = {}, bytes[9] = {};   // device copies of the nine lists, then the arena
+  size_t lds_limit = 0;
+  size_t off[10] = {}, bytes[10] = {};   // device copies of the ten lists, then the arena
   size_t off_arena = 0;
   std::string err;
 };
 
 inline size_t al256(size_t v) { return (v + 255) & ~size_t(255); }
 inline int32_t rmax_of(int32_t lt) { return (lt + 30) >> 5; }
-// bytes of one Toeplitz plane: the words the reads reach, rounded up to 64 mod 256
+// bytes of one Toeplitz digit plane: up to the fifth word of the last window
+// (byte X0 + 35), rounded up to 16
 inline int32_t ntp_of(int32_t lt) {
-  const int32_t need = (((32 * rmax_of(lt) + 31) + 31) / 4 + 1) * 4;
-  return need + ((64 - need) % 256 + 256) % 256;
+  const int32_t X0 = 32 * rmax_of(lt) + 31;
+  return (4 * ((X0 + 16) / 4 + 5) + 15) & ~15;
 }
 
 // The rounds of a set of values: (power, occurrence) -> products.
@@ -376,17 +499,26 @@ std::map<RoundKey, std::vector<std::pair<int32_t, const Prod*>>> rounds_of(const
   }
   return R;
 }
-size_t group_lds(const std::vector<const Value*>& vals, int32_t* ntp_out, int32_t* hp_out) {
-  int32_t ntp = ntp_of(1), hp = 32;
+// LDS bytes of a group's copied records.
+int32_t meta_bytes(int32_t rounds, int32_t ents, int32_t pars, int32_t bents, int32_t pents) {
+  return al16(rounds * (int)sizeof(GRound)) + al16(ents * (int)sizeof(GEntry)) + al16(pars * (int)sizeof(GParent)) +
+         al16(kCols * (int)sizeof(GOwn)) + al16(bents * 4) + al16(pents * 4) + al16(pars * 4);
+}
+// LDS of a group: every round's t and h planes, the tiles' sums, the records.
+size_t group_lds(const std::vector<const Value*>& vals) {
+  size_t bytes = 0;
+  int32_t nb = 0, nr = 0, ne = 0, nbe = 0;
+  for (const Value* v : vals) nb += (v->lout + 31) >> 5;
   for (auto& kv : rounds_of(vals)) {
     int32_t blocks = 1;
     for (auto& e : kv.second) blocks += (e.second->lh + 31) >> 5;
-    ntp = std::max(ntp, ntp_of(kv.second.front().second->lt));
-    hp = std::max(hp, 32 * blocks);
+    bytes += 4 * (size_t)ntp_of(kv.second.front().second->lt) + 4 * 32 * (size_t)blocks;
+    ++nr;
+    ne += (int32_t)kv.second.size();
+    nbe += blocks;
   }
-  if (ntp_out) *ntp_out = ntp;
-  if (hp_out) *hp_out = hp;
-  return (size_t)16 * ntp + (size_t)4 * hp;
+  const int32_t np = (int32_t)vals.size();
+  return ((bytes + 15) & ~size_t(15)) + (size_t)((nb + 31) >> 5) * kObufTile * 8 + meta_bytes(nr, ne, np, nbe, nr * np);
 }
 
 void add_group(CSched& S, const std::vector<const Value*>& vals, Launch& L) {
@@ -409,49 +541,94 @@ void add_group(CSched& S, const std::vector<const Value*>& vals, Launch& L) {
       if (m >= base[j] && m < base[j] + ((vals[j]->lout + 31) >> 5)) o = GOwn{(int32_t)j, base[j]};
     S.own.push_back(o);
   }
+  // rounds, their LDS planes, and the work of each tile (a list of (round,
+  // r_lo, r_hi) per tile)
+  std::vector<std::vector<GSeg>> work(G.ntiles);
+  int32_t lds = 0;
+  G.e_begin = (int32_t)S.ents.size();
+  G.b_begin = (int32_t)S.bent.size();
+  G.pe_begin = (int32_t)S.pent.size();
+  struct Col {
+    int32_t base, J;
+  };
   for (auto& kv : rounds_of(vals)) {
     GRound R{};
     const Prod* p0 = kv.second.front().second;
     R.t = p0->t;
     R.lt = p0->lt;
-    R.e_begin = (int32_t)S.ents.size();
-    R.col_begin = (int32_t)S.cols.size();
     R.b_begin = (int32_t)S.bent.size();
+    R.pe_begin = (int32_t)S.pent.size();
+    R.ntp = ntp_of(R.lt);
+    R.tbase = lds;
+    lds += 4 * R.ntp;
     const int32_t rmax = rmax_of(R.lt);
-    std::vector<GCol> col(kCols, GCol{0, 0, 0});
+    std::vector<Col> col(kCols, Col{0, 0});
+    std::vector<int32_t> pe(vals.size(), -1);
     int32_t blocks = 1;
     S.bent.push_back(-1);
     for (auto& e : kv.second) {
       const int32_t j = e.first;
       const int32_t J = (e.second->lh + 31) >> 5;
       for (int32_t k = 0; k < J; ++k) S.bent.push_back((int32_t)S.ents.size());
+      pe[j] = (int32_t)S.ents.size();
       S.ents.push_back(GEntry{e.second->h, e.second->lh, blocks});
       const int32_t nbj = (vals[j]->lout + 31) >> 5;
-      for (int32_t m = base[j]; m < base[j] + nbj; ++m) col[m] = GCol{blocks, base[j], J};
+      for (int32_t m = base[j]; m < base[j] + nbj; ++m) col[m] = Col{base[j], J};
       blocks += J;
     }
-    R.e_end = (int32_t)S.ents.size();
+    S.pent.insert(S.pent.end(), pe.begin(), pe.end());
     R.hblocks = blocks;
-    for (int32_t w = 0; w < kMaxTiles; ++w) {
+    R.hbase = lds;
+    lds += 4 * 32 * blocks;
+    const int32_t rd = (int32_t)S.rounds.size();
+    for (int32_t w = 0; w < G.ntiles; ++w) {
       int32_t lo = 1 << 30, hi = -1;
       for (int32_t m = 32 * w; m < 32 * w + 32; ++m) {
         if (col[m].J == 0) continue;
         lo = std::min(lo, std::max(0, m - col[m].base - col[m].J + 1));
         hi = std::max(hi, std::min(rmax, m - col[m].base));
       }
-      R.r_lo[w] = lo <= hi ? lo : 1;
-      R.r_hi[w] = lo <= hi ? hi : 0;
+      if (lo <= hi) work[w].push_back(GSeg{w, rd, lo, hi});
     }
-    S.cols.insert(S.cols.end(), col.begin(), col.end());
     S.rounds.push_back(R);
   }
   G.rd_end = (int32_t)S.rounds.size();
+  G.e_end = (int32_t)S.ents.size();
+  G.b_end = (int32_t)S.bent.size();
+  G.pe_end = (int32_t)S.pent.size();
+  G.obase = (lds + 15) & ~15;
+  G.mbase = G.obase + G.ntiles * kObufTile * 8;
+  lds = G.mbase + meta_bytes(G.rd_end - G.rd_begin, G.e_end - G.e_begin, G.p_end - G.p_begin, G.b_end - G.b_begin,
+                             G.pe_end - G.pe_begin);
+  // the tiles' work, tile by tile, cut into kWaves contiguous shares of
+  // (nearly) equal numbers of blocks
+  int64_t total = 0;
+  for (auto& wl : work)
+    for (auto& sg : wl) total += sg.r_hi - sg.r_lo + 1;
+  auto bound = [&](int32_t k) { return total * k / kWaves; };   // first block of share k
+  int64_t pos = 0;
+  int32_t wv = 0;
+  G.seg_begin[0] = (int32_t)S.segs.size();
+  for (auto& wl : work)
+    for (const GSeg& sg : wl)
+      for (int32_t lo = sg.r_lo; lo <= sg.r_hi;) {
+        while (wv + 1 < kWaves && pos >= bound(wv + 1)) {
+          G.seg_end[wv] = (int32_t)S.segs.size();
+          G.seg_begin[++wv] = (int32_t)S.segs.size();
+        }
+        const int64_t lim = wv + 1 < kWaves ? bound(wv + 1) : INT64_MAX;
+        const int32_t len = (int32_t)std::min<int64_t>(sg.r_hi - lo + 1, lim - pos);
+        S.segs.push_back(GSeg{sg.tile, sg.round, lo, lo + len - 1});
+        lo += len;
+        pos += len;
+      }
+  G.seg_end[wv] = (int32_t)S.segs.size();
+  for (int32_t k = wv + 1; k < kWaves; ++k) G.seg_begin[k] = G.seg_end[k] = (int32_t)S.segs.size();
   S.groups.push_back(G);
-  int32_t ntp = 0, hp = 0;
-  group_lds(vals, &ntp, &hp);
-  L.ntp = std::max(L.ntp, ntp);
-  L.hp = std::max(L.hp, hp);
-  L.waves = std::max(L.waves, G.ntiles);
+  L.lds = std::max(L.lds, lds);
+  // long shares keep the next block's operands in flight (two wavefronts per
+  // SIMD); short ones take the third wavefront instead
+  if ((total + kWaves - 1) / kWaves >= kPipeMinBlocks) L.pipe = 1;
 }
 
 // One dependency depth: its values packed into groups (matrix cores) or
@@ -461,11 +638,11 @@ void add_depth(CSched& S, const std::vector<Value>& vals) {
   for (const Value& v : vals) {
     int64_t sum_min = 0;
     for (const Prod& p : v.prods) sum_min += std::min(p.lt, p.lh);
-    bool ok = v.lout <= kCols * 32 && sum_min < kExactLimit;
-    if (ok) ok = group_lds({&v}, nullptr, nullptr) <= kMaxLds;
+    bool ok = v.lout > kValuMaxOut && v.lout <= kCols * 32 && sum_min < kExactLimit;
+    if (ok) ok = group_lds({&v}) <= S.lds_limit;
     (ok ? mf : va).push_back(&v);
   }
-  Launch L{1, (int32_t)S.groups.size(), 0, 1, 16, 32, 0};
+  Launch L{1, (int32_t)S.groups.size(), 0, 0, 0, 0};
   std::vector<const Value*> cur;
   int32_t blocks = 0;
   auto flush = [&]() {
@@ -473,7 +650,7 @@ void add_depth(CSched& S, const std::vector<Value>& vals) {
     if ((int32_t)S.groups.size() - L.begin == kMaxLaunchY) {
       L.end = (int32_t)S.groups.size();
       S.launches.push_back(L);
-      L = Launch{1, (int32_t)S.groups.size(), 0, 1, 16, 32, 0};
+      L = Launch{1, (int32_t)S.groups.size(), 0, 0, 0, 0};
     }
     add_group(S, cur, L);
     cur.clear();
@@ -484,7 +661,7 @@ void add_depth(CSched& S, const std::vector<Value>& vals) {
     if (!cur.empty()) {
       std::vector<const Value*> trial = cur;
       trial.push_back(v);
-      if (blocks + nb > kCols || group_lds(trial, nullptr, nullptr) > kMaxLds) flush();
+      if (blocks + nb > kCols || group_lds(trial) > S.lds_limit) flush();
     }
     cur.push_back(v);
     blocks += nb;
@@ -493,7 +670,7 @@ void add_depth(CSched& S, const std::vector<Value>& vals) {
   L.end = (int32_t)S.groups.size();
   if (L.end > L.begin) S.launches.push_back(L);
   for (size_t b = 0; b < va.size(); b += kMaxLaunchY) {
-    Launch V{0, (int32_t)S.vpars.size(), 0, 0, 0, 0, 0};
+    Launch V{0, (int32_t)S.vpars.size(), 0, 0, 0, 0};
     for (size_t k = b; k < std::min(va.size(), b + kMaxLaunchY); ++k) {
       const Value* v = va[k];
       CParent P{v->out, v->coef_node, (int32_t)S.vch.size(), 0, v->lout};
@@ -507,9 +684,21 @@ void add_depth(CSched& S, const std::vector<Value>& vals) {
   }
 }
 
+// LDS a workgroup may allocate on the current device (64 KB if unknown).
+size_t lds_limit() {
+  int dev = 0, v = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess || v <= 0) {
+    (void)hipGetLastError();
+    return 64 * 1024;
+  }
+  return (size_t)v;
+}
+
 CSched build_csched(const fpe_tree* t, int32_t dq) {
   CSched S;
   S.dq = dq;
+  S.lds_limit = lds_limit();
   const int64_t N = (int64_t)t->nodes.size();
   int32_t dp = 0;
   for (int64_t i = 0; i < N; ++i) dp = std::max(dp, t->exps[i * t->nvars]);
@@ -600,13 +789,13 @@ CSched build_csched(const fpe_tree* t, int32_t dq) {
   for (size_t d = 1; d < by_depth.size(); ++d)
     if (!by_depth[d].empty()) add_depth(S, by_depth[d]);
   S.arena_words = (words + 63) & ~int64_t(63);
-  const size_t sizes[9] = {S.groups.size() * sizeof(GGroup), S.gpars.size() * sizeof(GParent),
-                           S.rounds.size() * sizeof(GRound), S.ents.size() * sizeof(GEntry),
-                           S.cols.size() * sizeof(GCol),     S.own.size() * sizeof(GOwn),
-                           S.vpars.size() * sizeof(CParent), S.vch.size() * sizeof(CChild),
-                           S.bent.size() * sizeof(int32_t)};
+  const size_t sizes[10] = {S.groups.size() * sizeof(GGroup), S.gpars.size() * sizeof(GParent),
+                            S.rounds.size() * sizeof(GRound), S.ents.size() * sizeof(GEntry),
+                            S.own.size() * sizeof(GOwn),      S.bent.size() * sizeof(int32_t),
+                            S.pent.size() * sizeof(int32_t),  S.segs.size() * sizeof(GSeg),
+                            S.vpars.size() * sizeof(CParent), S.vch.size() * sizeof(CChild)};
   size_t o = 0;
-  for (int k = 0; k < 9; ++k) {
+  for (int k = 0; k < 10; ++k) {
     S.off[k] = o;
     S.bytes[k] = sizes[k];
     o = al256(o + sizes[k]);
@@ -676,18 +865,18 @@ fpe_status launch_compose_levels(const fpe_tree* t, const uint32_t* q, int32_t d
   char* base = (char*)ws;
   // the schedule lives as long as the tree's cache entry, so the copies read
   // live memory whenever they run
-  const void* src[9] = {S->groups.data(), S->gpars.data(), S->rounds.data(), S->ents.data(), S->cols.data(),
-                        S->own.data(),    S->vpars.data(), S->vch.data(),    S->bent.data()};
+  const void* src[10] = {S->groups.data(), S->gpars.data(), S->rounds.data(), S->ents.data(), S->own.data(),
+                         S->bent.data(),   S->pent.data(),  S->segs.data(),  S->vpars.data(), S->vch.data()};
   hipError_t e = hipSuccess;
-  for (int k = 0; k < 9 && e == hipSuccess; ++k)
+  for (int k = 0; k < 10 && e == hipSuccess; ++k)
     if (S->bytes[k]) e = hipMemcpyAsync(base + S->off[k], src[k], S->bytes[k], hipMemcpyHostToDevice, st);
   if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("composition: ") + hipGetErrorString(e));
   GLists Ls{(const GGroup*)(base + S->off[0]), (const GParent*)(base + S->off[1]),
             (const GRound*)(base + S->off[2]), (const GEntry*)(base + S->off[3]),
-            (const GCol*)(base + S->off[4]),   (const GOwn*)(base + S->off[5]),
-            (const int32_t*)(base + S->off[8])};
-  const CParent* vpars = (const CParent*)(base + S->off[6]);
-  const CChild* vch = (const CChild*)(base + S->off[7]);
+            (const GOwn*)(base + S->off[4]),   (const int32_t*)(base + S->off[5]),
+            (const int32_t*)(base + S->off[6]), (const GSeg*)(base + S->off[7])};
+  const CParent* vpars = (const CParent*)(base + S->off[8]);
+  const CChild* vch = (const CChild*)(base + S->off[9]);
   CBases B{(uint32_t*)(base + S->off_arena), q, out, dev_view(t).coef_rows, S->arena_words, (int64_t)dq + 1,
            S->lmax, (int64_t)t->nodes.size()};
   for (const Launch& L : S->launches) {
@@ -695,8 +884,16 @@ fpe_status launch_compose_levels(const fpe_tree* t, const uint32_t* q, int32_t d
     if (L.mfma) {
       GLists Lg = Ls;
       Lg.groups += L.begin;
-      const size_t lds = (size_t)16 * L.ntp + (size_t)4 * L.hp;
-      hipLaunchKernelGGL(k_cm_mfma, dim3((unsigned)t->batch, n), dim3(64 * L.waves), lds, st, Lg, B, L.ntp, L.hp);
+      const void* k = L.pipe ? (const void*)k_cm_mfma<true> : (const void*)k_cm_mfma<false>;
+      if (L.lds > 64 * 1024) {
+        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, L.lds);
+        if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("composition LDS: ") + hipGetErrorString(e));
+      }
+      if (L.pipe)
+        hipLaunchKernelGGL(k_cm_mfma<true>, dim3((unsigned)t->batch, n), dim3(64 * kWaves), (size_t)L.lds, st, Lg, B);
+      else
+        hipLaunchKernelGGL(k_cm_mfma<false>, dim3((unsigned)t->batch, n), dim3(64 * kWaves), (size_t)L.lds, st, Lg,
+                           B);
     } else {
       const int64_t gx = (t->batch * L.max_lout + 255) / 256;
       hipLaunchKernelGGL(k_cm_valu, dim3((unsigned)gx, n), dim3(256), 0, st, vpars + L.begin, vch, B, t->batch);
