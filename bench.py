@@ -44,6 +44,8 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP32_VALU_PEAK = 256 * 128 * 2.4e9
 FP64_FMA_PEAK = 256 * 64 * 2.4e9
+# dense int8 matrix-core operations per second (published; a multiply-add is two)
+I8_MFMA_PEAK = 5.0e15
 # FP32 operations of one compensated multiply-add a * X + b (X read as two
 # floats): product and its error by fma (2), two cross terms (2), TwoSum (6),
 # two low-order adds (2), FastTwoSum (3), then the running error bound:
@@ -51,10 +53,9 @@ FP64_FMA_PEAK = 256 * 64 * 2.4e9
 # 20 u^2 |p| (1 fma) and 6 u^2 |b| (1 fma when b is an accumulator; a
 # coefficient's term is a constant of the op).  Per step kind: LEAF_ADD
 # a X + top 17, NODE_OPEN top X + b 17, LEAF_OPEN a X + b 16, NODE_ADD
-# top X + below 18; END (once per point) is not counted.  The condition sum (1 more fma) is computed only when per-point
-# condition numbers are requested, which the timed step does not do (the
-# condition numbers of the workload are reported from the oracle's sample
-# instead).
+# top X + below 18; END (once per point) is not counted.  The condition sum
+# (1 more fma) is computed when per-point condition numbers are requested,
+# which the timed step does.
 DF32_OPS_BY_KIND = (17, 17, 16, 18, 0)
 # The algorithmic FP32 operation count of one compensated step that the
 # roofline fraction is quoted on: TwoProd 2, TwoSum 6, first-order error
@@ -530,8 +531,11 @@ def bigpoint_phase(fpe, torch, dev, reps: int = 3):
     return res
 
 
-def compose_phase(fpe, fpe_inputs, torch, dev, reps: int = 3):
-    """4096 instances of p(q(x)) mod 2^31-1, deg p = 255, deg q = 15."""
+def compose_phase(fpe, fpe_inputs, torch, dev, reps: int = 10):
+    """4096 instances of p(q(x)) mod 2^31-1, deg p = 255, deg q = 15: the time
+    per call over `reps` back-to-back calls (the throughput of a stream of
+    batches), and the median time of single calls with the device idle
+    before each (latency, including the schedule's upload and the launches)."""
     inp = fpe_inputs.compose_batch()
     b, dp1 = inp.p.shape
     ex = np.arange(dp1, dtype=np.int32).reshape(-1, 1)
@@ -543,26 +547,43 @@ def compose_phase(fpe, fpe_inputs, torch, dev, reps: int = 3):
         ws = torch.empty(int(fpe.lib.fpe_compose_workspace_bytes(t.handle, inp.q.shape[1] - 1)) + 256,
                          dtype=torch.uint8, device=dev)
         torch.cuda.synchronize()
-        ms = []
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
         for _ in range(reps):
-            e0 = torch.cuda.Event(enable_timing=True)
-            e1 = torch.cuda.Event(enable_timing=True)
+            fpe.compose(t, q, out=out, workspace=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        m = e0.elapsed_time(e1) / reps
+        single = []
+        for _ in range(3):
             e0.record()
             fpe.compose(t, q, out=out, workspace=ws)
             e1.record()
             torch.cuda.synchronize()
-            ms.append(e0.elapsed_time(e1))
-        m = float(np.median(ms))
+            single.append(e0.elapsed_time(e1))
         macs = compose_macs(t, inp.q.shape[1] - 1) * b
-        res[s] = {"ms": m, "instances_per_s": b / (m * 1e-3), "mod_macs": macs, "mod_macs_per_s": macs / (m * 1e-3),
-                  "frac_of_mad_u64_peak": macs / (m * 1e-3) / FP64_FMA_PEAK}
+        res[s] = {"ms": m, "single_call_ms": float(np.median(single)), "instances_per_s": b / (m * 1e-3),
+                  "mod_macs": macs, "mod_macs_per_s": macs / (m * 1e-3),
+                  # the product method fpe_compose picks: the level walk on the matrix
+                  # cores for the divide-and-conquer trees, the fused VALU walk for
+                  # Hörner's 255 levels
+                  "product": "fused" if s == "horner" else "mfma"}
+        if s == "horner":
+            res[s]["frac_of_mad_u64_peak"] = macs / (m * 1e-3) / FP64_FMA_PEAK
+        else:
+            # one modular multiply-add = 16 products of balanced 8-bit digits
+            # (2 ops each) on the int8 matrix cores
+            res[s]["i8_ops"] = 32.0 * macs
+            res[s]["frac_of_i8_mfma_peak"] = 32.0 * macs / (m * 1e-3) / I8_MFMA_PEAK
     return res
 
 
 def compose_methods_phase(fpe, fpe_inputs, torch, dev, reps: int = 3):
     """Composition by product method: the 4096 x (255 o 15) workload with the
-    fused walk, and with the op-by-op walk using schoolbook or transform
-    (subquadratic) products; then larger compositions (64 instances of
+    fused walk, with the op-by-op walk using schoolbook or transform
+    (subquadratic) products, and with the level walk on the matrix cores;
+    then larger compositions (64 instances of
     degree 511, 512 and 1023 in p, degree 15 in q), where the transform
     products make the divide-and-conquer schemes pay off against Hörner and
     the term count just past a power of two shows Estrin's staircase."""
@@ -591,7 +612,7 @@ def compose_methods_phase(fpe, fpe_inputs, torch, dev, reps: int = 3):
     c4 = {}
     for s in ("balanced", "estrin", "horner"):
         t = fpe.Tree(ex, inp.p.astype(np.uint64), s, fpe.MODP, fpe.P31).upload(dev)
-        c4[s] = {m: timed(t, q, m) for m in ("fused", "schoolbook", "ntt")}
+        c4[s] = {m: timed(t, q, m) for m in ("fused", "schoolbook", "ntt", "mfma")}
     res["4096x255o15_ms"] = c4
     g = np.random.default_rng([13075655, 940])
     for dp in (511, 512, 1023):
@@ -624,6 +645,8 @@ def main():
                     help="run only the served stream (for a profiler run of the fused kernels) and print its results")
     ap.add_argument("--probes-only", action="store_true",
                     help="run only the rate probes (for a profiler run of the probe kernels) and print them")
+    ap.add_argument("--compose-only", action="store_true",
+                    help="run only the 4096 x (255 o 15) composition (for a profiler run of its kernels) and print it")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="after the timed steps, copy a device buffer of this many bytes three times "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -645,6 +668,9 @@ def main():
         return
     if args.probes_only:
         print(json.dumps({"probes": probe_phase(torch, dev)}), flush=True)
+        return
+    if args.compose_only:
+        print(json.dumps({"compose_4096": compose_phase(fpe, fpe_inputs, torch, dev)}), flush=True)
         return
     degrees = (3000, 5000)
     schemes = ("balanced", "estrin", "horner")

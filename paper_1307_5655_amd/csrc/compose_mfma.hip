@@ -37,7 +37,9 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 
 #include "fpe_internal.h"
@@ -54,7 +56,6 @@ constexpr int kMaxTiles = 4;             // tiles (32 x 32 outputs) of one workg
 constexpr int kWaves = 4;                // wavefronts of one workgroup
 constexpr int kCols = 32 * kMaxTiles;    // output blocks of 32 coefficients per workgroup
 constexpr int kObufTile = 32 * 33;       // 64-bit sums of one tile in LDS (rows padded to 33)
-constexpr int64_t kPipeMinBlocks = 16;   // shares of at least this many blocks use two operand sets
 constexpr int32_t kValuMaxOut = 64;      // values this short go to the VALU kernel (latency-bound either way)
 constexpr int kGroups = 7;               // digit pairs (s, a) grouped by s + a
 constexpr int kMaxLaunchY = 65535;
@@ -226,11 +227,10 @@ __host__ __device__ constexpr int al16(int v) { return (v + 15) & ~15; }
 // each plane as two halves (bytes 0..15 of every block, then 16..31) so the
 // 16-byte reads of consecutive lanes are consecutive.  The tiles' sums are
 // 32 x 33 words per tile (row-major, padded), residues < p added by at most
-// four wavefronts.  kPipe: two operand sets, the next block's loads in
-// flight during the current block's products (two wavefronts per SIMD);
-// otherwise one set and three wavefronts per SIMD.
-template <bool kPipe>
-__global__ __launch_bounds__(256, kPipe ? 2 : 3) void k_cm_mfma(GLists Ls, CBases B) {
+// four wavefronts.  Each block step loads and cuts one Toeplitz plane at a
+// time, so a plane's loads are in flight while the previous plane's products
+// run; three wavefronts per SIMD hide the rest.
+__global__ __launch_bounds__(256, 3) void k_cm_mfma(GLists Ls, CBases B) {
   extern __shared__ __align__(16) uint8_t lds[];
   const GGroup G = Ls.groups[blockIdx.y];
   const int64_t inst = blockIdx.x;
@@ -353,61 +353,21 @@ __global__ __launch_bounds__(256, kPipe ? 2 : 3) void k_cm_mfma(GLists Ls, CBase
     const uint32_t* tp = (const uint32_t*)(lds + R.tbase) + (s0 >> 2);
     const uint8_t* hp = lds + R.hbase + 16 * hh * R.hblocks;
     const int hpb = 32 * R.hblocks;
-    auto load = [&](int r, uint32_t (&d)[4][5], u32x4 (&h)[4]) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s)
-#pragma unroll
-        for (int k = 0; k < 5; ++k) d[s][k] = tp[s * ntw - 8 * r + k];
+    for (int r = S.r_lo; r <= S.r_hi; ++r) {
       const int jb = jb0 - r;
       const int off = 16 * ((unsigned)jb < (unsigned)J ? hblk + jb : 0);
+      u32x4 h[4];
 #pragma unroll
       for (int s = 0; s < 4; ++s) h[s] = *(const u32x4*)(hp + s * hpb + off);
-    };
-    auto mma = [&](const uint32_t (&d)[4][5], const u32x4 (&h)[4]) {
-      i8x16 A[4];
 #pragma unroll
-      for (int s = 0; s < 4; ++s) A[s] = toeplitz_bytes(d[s], e);
+      for (int a = 0; a < 4; ++a) {
+        uint32_t w[5];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+        for (int k = 0; k < 5; ++k) w[k] = tp[a * ntw - 8 * r + k];
+        const i8x16 A = toeplitz_bytes(w, e);
 #pragma unroll
         for (int s = 0; s < 4; ++s)
-          acc[a + s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[a], __builtin_bit_cast(i8x16, h[s]), acc[a + s], 0,
-                                                              0, 0);
-    };
-    uint32_t d0[4][5];
-    u32x4 h0[4];
-    if constexpr (kPipe) {
-      uint32_t d1[4][5];
-      u32x4 h1[4];
-      int r = S.r_lo;
-      load(r, d0, h0);
-      for (; r + 1 <= S.r_hi; r += 2) {
-        load(r + 1, d1, h1);
-        mma(d0, h0);
-        if (r + 2 <= S.r_hi) load(r + 2, d0, h0);
-        mma(d1, h1);
-      }
-      if (r == S.r_hi) mma(d0, h0);
-    } else {
-      // one plane of the Toeplitz operand at a time: its words are loaded
-      // while the previous plane's products run
-      const int off0 = jb0;
-      for (int r = S.r_lo; r <= S.r_hi; ++r) {
-        const int jb = off0 - r;
-        const int off = 16 * ((unsigned)jb < (unsigned)J ? hblk + jb : 0);
-#pragma unroll
-        for (int s = 0; s < 4; ++s) h0[s] = *(const u32x4*)(hp + s * hpb + off);
-#pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          uint32_t w[5];
-#pragma unroll
-          for (int k = 0; k < 5; ++k) w[k] = tp[a * ntw - 8 * r + k];
-          const i8x16 A = toeplitz_bytes(w, e);
-#pragma unroll
-          for (int s = 0; s < 4; ++s)
-            acc[a + s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, __builtin_bit_cast(i8x16, h0[s]), acc[a + s], 0,
-                                                                0, 0);
-        }
+          acc[a + s] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A, __builtin_bit_cast(i8x16, h[s]), acc[a + s], 0, 0, 0);
       }
     }
   }
@@ -456,8 +416,26 @@ struct Launch {
   int32_t begin, end;   // groups (mfma) or VALU parents
   int32_t lds;          // dynamic LDS bytes (mfma)
   int32_t max_lout;
-  int32_t pipe;         // the kernel with two operand sets (groups with long shares)
 };
+// The schedule's lists in one pinned host buffer, copied to the workspace by
+// one asynchronous copy per call; freed once the last copy from it is done.
+struct PinnedLists {
+  uint8_t* p = nullptr;
+  std::vector<uint8_t> pageable;   // if pinned memory is unavailable
+  hipEvent_t done = nullptr;       // recorded after each copy from p
+  PinnedLists() = default;
+  PinnedLists(const PinnedLists&) = delete;
+  PinnedLists& operator=(const PinnedLists&) = delete;
+  ~PinnedLists() {
+    if (done) {
+      (void)hipEventSynchronize(done);
+      (void)hipEventDestroy(done);
+    }
+    if (p) (void)hipHostFree(p);
+  }
+  uint8_t* data() { return p ? p : pageable.data(); }
+};
+
 struct CSched {
   int32_t dq = 0;
   std::vector<GGroup> groups;
@@ -474,6 +452,7 @@ struct CSched {
   size_t lds_limit = 0;
   size_t off[10] = {}, bytes[10] = {};   // device copies of the ten lists, then the arena
   size_t off_arena = 0;
+  std::shared_ptr<PinnedLists> lists;
   std::string err;
 };
 
@@ -626,9 +605,6 @@ void add_group(CSched& S, const std::vector<const Value*>& vals, Launch& L) {
   for (int32_t k = wv + 1; k < kWaves; ++k) G.seg_begin[k] = G.seg_end[k] = (int32_t)S.segs.size();
   S.groups.push_back(G);
   L.lds = std::max(L.lds, lds);
-  // long shares keep the next block's operands in flight (two wavefronts per
-  // SIMD); short ones take the third wavefront instead
-  if ((total + kWaves - 1) / kWaves >= kPipeMinBlocks) L.pipe = 1;
 }
 
 // One dependency depth: its values packed into groups (matrix cores) or
@@ -642,7 +618,7 @@ void add_depth(CSched& S, const std::vector<Value>& vals) {
     if (ok) ok = group_lds({&v}) <= S.lds_limit;
     (ok ? mf : va).push_back(&v);
   }
-  Launch L{1, (int32_t)S.groups.size(), 0, 0, 0, 0};
+  Launch L{1, (int32_t)S.groups.size(), 0, 0, 0};
   std::vector<const Value*> cur;
   int32_t blocks = 0;
   auto flush = [&]() {
@@ -650,7 +626,7 @@ void add_depth(CSched& S, const std::vector<Value>& vals) {
     if ((int32_t)S.groups.size() - L.begin == kMaxLaunchY) {
       L.end = (int32_t)S.groups.size();
       S.launches.push_back(L);
-      L = Launch{1, (int32_t)S.groups.size(), 0, 0, 0, 0};
+      L = Launch{1, (int32_t)S.groups.size(), 0, 0, 0};
     }
     add_group(S, cur, L);
     cur.clear();
@@ -670,7 +646,7 @@ void add_depth(CSched& S, const std::vector<Value>& vals) {
   L.end = (int32_t)S.groups.size();
   if (L.end > L.begin) S.launches.push_back(L);
   for (size_t b = 0; b < va.size(); b += kMaxLaunchY) {
-    Launch V{0, (int32_t)S.vpars.size(), 0, 0, 0, 0};
+    Launch V{0, (int32_t)S.vpars.size(), 0, 0, 0};
     for (size_t k = b; k < std::min(va.size(), b + kMaxLaunchY); ++k) {
       const Value* v = va[k];
       CParent P{v->out, v->coef_node, (int32_t)S.vch.size(), 0, v->lout};
@@ -801,6 +777,21 @@ CSched build_csched(const fpe_tree* t, int32_t dq) {
     o = al256(o + sizes[k]);
   }
   S.off_arena = o;
+  S.lists = std::make_shared<PinnedLists>();
+  PinnedLists& H = *S.lists;
+  if (hipHostMalloc((void**)&H.p, std::max<size_t>(o, 256), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&H.done, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    if (H.p) (void)hipHostFree(H.p);
+    H.p = nullptr;
+    H.done = nullptr;
+    H.pageable.assign(std::max<size_t>(o, 256), 0);
+  }
+  const void* src[10] = {S.groups.data(), S.gpars.data(), S.rounds.data(), S.ents.data(), S.own.data(),
+                         S.bent.data(),   S.pent.data(),  S.segs.data(),  S.vpars.data(), S.vch.data()};
+  std::memset(H.data(), 0, o);
+  for (int k = 0; k < 10; ++k)
+    if (S.bytes[k]) std::memcpy(H.data() + S.off[k], src[k], S.bytes[k]);
   return S;
 }
 
@@ -863,13 +854,10 @@ fpe_status launch_compose_levels(const fpe_tree* t, const uint32_t* q, int32_t d
   if (((uintptr_t)ws) & 255) return fail(FPE_EINVAL, "workspace must be 256-byte aligned");
   hipStream_t st = (hipStream_t)stream;
   char* base = (char*)ws;
-  // the schedule lives as long as the tree's cache entry, so the copies read
-  // live memory whenever they run
-  const void* src[10] = {S->groups.data(), S->gpars.data(), S->rounds.data(), S->ents.data(), S->own.data(),
-                         S->bent.data(),   S->pent.data(),  S->segs.data(),  S->vpars.data(), S->vch.data()};
-  hipError_t e = hipSuccess;
-  for (int k = 0; k < 10 && e == hipSuccess; ++k)
-    if (S->bytes[k]) e = hipMemcpyAsync(base + S->off[k], src[k], S->bytes[k], hipMemcpyHostToDevice, st);
+  // the lists stay alive until this copy has run (their buffer waits for
+  // the event before it is freed)
+  hipError_t e = hipMemcpyAsync(base, S->lists->data(), S->off_arena, hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && S->lists->done) e = hipEventRecord(S->lists->done, st);
   if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("composition: ") + hipGetErrorString(e));
   GLists Ls{(const GGroup*)(base + S->off[0]), (const GParent*)(base + S->off[1]),
             (const GRound*)(base + S->off[2]), (const GEntry*)(base + S->off[3]),
@@ -884,16 +872,17 @@ fpe_status launch_compose_levels(const fpe_tree* t, const uint32_t* q, int32_t d
     if (L.mfma) {
       GLists Lg = Ls;
       Lg.groups += L.begin;
-      const void* k = L.pipe ? (const void*)k_cm_mfma<true> : (const void*)k_cm_mfma<false>;
-      if (L.lds > 64 * 1024) {
-        e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, L.lds);
-        if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("composition LDS: ") + hipGetErrorString(e));
+      if (L.lds > 64 * 1024) {   // raise the kernel's dynamic LDS limit once per larger size
+        static std::mutex mu;
+        static int32_t set_to = 64 * 1024;
+        std::lock_guard<std::mutex> lk(mu);
+        if (L.lds > set_to) {
+          e = hipFuncSetAttribute((const void*)k_cm_mfma, hipFuncAttributeMaxDynamicSharedMemorySize, L.lds);
+          if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("composition LDS: ") + hipGetErrorString(e));
+          set_to = L.lds;
+        }
       }
-      if (L.pipe)
-        hipLaunchKernelGGL(k_cm_mfma<true>, dim3((unsigned)t->batch, n), dim3(64 * kWaves), (size_t)L.lds, st, Lg, B);
-      else
-        hipLaunchKernelGGL(k_cm_mfma<false>, dim3((unsigned)t->batch, n), dim3(64 * kWaves), (size_t)L.lds, st, Lg,
-                           B);
+      hipLaunchKernelGGL(k_cm_mfma, dim3((unsigned)t->batch, n), dim3(64 * kWaves), (size_t)L.lds, st, Lg, B);
     } else {
       const int64_t gx = (t->batch * L.max_lout + 255) / 256;
       hipLaunchKernelGGL(k_cm_valu, dim3((unsigned)gx, n), dim3(256), 0, st, vpars + L.begin, vch, B, t->batch);
