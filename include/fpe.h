@@ -252,15 +252,14 @@ size_t fpe_compose_workspace_bytes(const fpe_tree* t, int32_t dq);
  *                           exactly by number-theoretic transforms modulo three
  *                           primes below 2^31 and Garner's recombination
  *                           (subquadratic products, up to 2^14 coefficients)
- *   FPE_PRODUCT_MFMA        the tree walked level by level (the nodes of one
- *                           height, for all instances, in one launch; Section 1's
- *                           definition u(N) = c(N) + sum_C u(C) q^d(C)), each
- *                           product of at least 256 output coefficients an exact
- *                           integer matrix product on the matrix cores (balanced
- *                           8-bit digits of the centred residues, Toeplitz
- *                           blocks, 32x32x32 int8 MFMA), smaller ones on a
- *                           schoolbook kernel; nodes of up to 4096 output
- *                           coefficients on the matrix cores, longer ones schoolbook
+ *   FPE_PRODUCT_MFMA        the tree walked by levels (every value whose operands
+ *                           exist, for all instances, in one launch; Section 1's
+ *                           definition u(N) = c(N) + sum_C u(C) q^d(C), powers by
+ *                           the chain of Section 2.2), each value of 65 to 4096
+ *                           output coefficients an exact integer matrix product
+ *                           on the matrix cores (balanced 8-bit digits of the
+ *                           centred residues, Toeplitz blocks, 32x32x32 int8
+ *                           MFMA), shorter and longer ones on a schoolbook kernel
  *   FPE_PRODUCT_AUTO        deg_p * dq + 1 <= 4096: MFMA when the level walk
  *                           takes at most 64 launches (divide-and-conquer
  *                           trees), else FUSED; beyond 4096: NTT
