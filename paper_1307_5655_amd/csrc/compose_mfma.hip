@@ -25,7 +25,8 @@
 // groups are recombined with 2^(8 g) = 2^(8 g mod 31) mod p.
 //
 // A workgroup computes a group of values of one instance laid side by side
-// in the columns (output blocks) of up to four tiles, one wavefront per tile.
+// in the columns (output blocks) of up to four tiles; its four wavefronts
+// share the tiles' work evenly.
 // Their products are taken in rounds, one per power q^d: the power is the
 // Toeplitz operand shared by every value of the group that multiplies it,
 // and each value's factor sits in its own blocks of the h operand, so the
