@@ -15,6 +15,51 @@ const char* last_error();
 namespace {
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// The plain FP64 walk's program for chain-like trees (depth <= 2, every power
+// in the table): maximal sequences of at least kRunMinOps depth-1 NODE_OPEN
+// steps by powers of the first table entry become run records (kRunCode).
+// Other trees keep ops64.
+void build_runs(fpe_tree* t) {
+  t->ops64r.clear();
+  t->runc.clear();
+  if (t->domain != FPE_F64 || t->depth > 2 || t->n_offtable > 0 || t->n_table < 1 || t->table_deg[0] <= 0) return;
+  const int32_t v0 = t->table_var[0], d0 = t->table_deg[0];
+  auto unit_steps = [&](const OpF64& o) -> int {   // steps of x^d0 the op is; 0: not a chain step
+    if (op_kind(o.info) != kNodeOpen || op_level(o.info) != 1 || op_pidx2(o.info) != kNoPair) return 0;
+    const uint32_t p = op_pidx(o.info);
+    if (p == kOffTable || (int32_t)p >= t->n_table || t->table_var[p] != v0 || t->table_deg[p] % d0) return 0;
+    const int k = t->table_deg[p] / d0;
+    return k <= kRunMaxGap ? k : 0;
+  };
+  const size_t n = t->ops64.size();
+  std::vector<OpF64> prog;
+  std::vector<uint64_t> coefs;
+  bool any = false;
+  for (size_t i = 0; i < n;) {
+    size_t j = i;
+    while (j < n && unit_steps(t->ops64[j]) > 0) ++j;
+    if (j - i >= (size_t)kRunMinOps) {
+      OpF64 r = t->ops64[i];
+      r.a = coefs.size();
+      for (size_t k = i; k < j; ++k) {
+        for (int z = 1; z < unit_steps(t->ops64[k]); ++z) coefs.push_back(0);   // +0.0
+        coefs.push_back(t->ops64[k].b);
+      }
+      r.b = coefs.size() - r.a;
+      r.deg = kRunCode << 20;
+      prog.push_back(r);
+      any = true;
+      i = j;
+    } else {
+      prog.push_back(t->ops64[i]);
+      ++i;
+    }
+  }
+  if (!any) return;
+  t->ops64r = std::move(prog);
+  t->runc = std::move(coefs);
+}
+
 void layout(fpe_tree* t) {
   // bound data of the compensated walk, from the node array
   for (int j = 0; j < 8; ++j) t->deg_max[j] = 0;
@@ -30,6 +75,7 @@ void layout(fpe_tree* t) {
   // the tree so that the upload is an asynchronous copy from live memory
   t->coef_rows32.clear();
   if (t->domain == FPE_MODP && t->modulus == kP31) t->coef_rows32.assign(t->coef_rows.begin(), t->coef_rows.end());
+  build_runs(t);
   size_t off = 0;
   // each op array is followed by kOpTail zero records (the walk reads ahead)
   t->off_ops64 = off;
@@ -40,6 +86,10 @@ void layout(fpe_tree* t) {
   off = align256(off + std::max<size_t>(t->chain.size(), 1) * sizeof(ChainStep));
   t->off_coef = off;
   if (t->domain == FPE_MODP && t->modulus == kP31) off = align256(off + t->coef_rows.size() * sizeof(uint32_t));
+  t->off_ops64r = off;
+  if (!t->ops64r.empty()) off = align256(off + (t->ops64r.size() + kOpTail) * sizeof(OpF64));
+  t->off_runc = off;
+  if (!t->runc.empty()) off = align256(off + t->runc.size() * sizeof(uint64_t));
   t->dev_bytes = std::max<size_t>(off, 256);
 }
 }  // namespace
@@ -48,6 +98,8 @@ DevTree dev_view(const fpe_tree* t) {
   DevTree d{};
   const char* b = (const char*)t->dev;
   d.ops64 = (const OpF64*)(b + t->off_ops64);
+  d.ops64r = t->ops64r.empty() ? d.ops64 : (const OpF64*)(b + t->off_ops64r);
+  d.runc = (const uint64_t*)(b + t->off_runc);
   d.ops32 = (const OpF32*)(b + t->off_ops32);
   d.chain = (const ChainStep*)(b + t->off_chain);
   d.coef_rows = (const uint32_t*)(b + t->off_coef);
@@ -161,6 +213,16 @@ fpe_status fpe_tree_upload(fpe_tree* t, void* dev_buf, size_t bytes, void* strea
   if (e == hipSuccess && t->domain == FPE_MODP && t->modulus == kP31)
     e = hipMemcpyAsync(b + t->off_coef, t->coef_rows32.data(), t->coef_rows32.size() * sizeof(uint32_t),
                        hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !t->ops64r.empty()) {
+    e = hipMemcpyAsync(b + t->off_ops64r, t->ops64r.data(), t->ops64r.size() * sizeof(OpF64), hipMemcpyHostToDevice,
+                       st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b + t->off_ops64r + t->ops64r.size() * sizeof(OpF64), kZero64, sizeof kZero64,
+                         hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b + t->off_runc, t->runc.data(), t->runc.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
+                         st);
+  }
   if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
   t->dev = dev_buf;
   return FPE_OK;

@@ -34,12 +34,17 @@ static void go(const KernelLaunch& L, double* out) {
 
 void launch_f64(const KernelLaunch& L, double* out) {
   const bool d2 = L.tr.depth <= 2, d6 = L.tr.depth <= 6, d8 = L.tr.depth <= 8;
+  // the chain-like kernels read the program with runs (every width, so the
+  // bits do not depend on the points per lane)
+  KernelLaunch R = L;
+  R.tr.ops64 = L.tr.ops64r;
   if (L.offt) {
     if (d8) go<8, 1, true>(L, out); else go<kMaxDepth, 1, true>(L, out);
-  } else if (L.ppl >= 8 && d2) {
-    go<2, 8, false>(L, out);
-  } else if (L.ppl >= 4 && d2) {
-    go<2, 4, false>(L, out);
+  } else if (d2) {
+    if (L.ppl >= 8) go<2, 8, false>(R, out);
+    else if (L.ppl >= 4) go<2, 4, false>(R, out);
+    else if (L.ppl >= 2) go<2, 2, false>(R, out);
+    else go<2, 1, false>(R, out);
   } else if (L.ppl >= 4 && d6) {
     go<6, 4, false>(L, out);
   } else if (L.ppl >= 4 && d8) {

@@ -106,6 +106,16 @@ static_assert(sizeof(OpF32) == 32, "OpF32 is one 32-byte scalar load");
 // three records past END
 constexpr int kOpTail = 3;
 
+// A run record (plain FP64 walk of chain-like trees): b consecutive steps
+// top = top * X0 + c at depth 1, X0 the first register power, with the
+// coefficients c at runc[a .. a + b).  A Hörner step by x^(k d0) (d0 the
+// degree of table entry 0, k <= kRunMaxGap) is k such steps, the first k - 1
+// with c = 0 (exact in real arithmetic: (t x^d0 + 0) x^d0 = t x^(2 d0)).
+// Its dispatch code lies outside the switch's range.
+constexpr uint32_t kRunCode = 0x800;
+constexpr int kRunMaxGap = 4;
+constexpr int kRunMinOps = 8;
+
 // Power chain (fast exponentiation, Section 2.2): table[dst] = x_var (LOAD)
 // or table[s1] * table[s2] (MUL), in order.  Entries 0..n_used-1 are the ones
 // the walk reads, sorted by how often it reads them.
@@ -124,6 +134,8 @@ struct ChainStep {
 // base pointer; passed by value as a kernel argument).
 struct DevTree {
   const OpF64* ops64;
+  const OpF64* ops64r;         // the FP64 chain walk's program: ops64 with runs (see kRunCode)
+  const uint64_t* runc;        // FP64 bits of the runs' coefficients
   const OpF32* ops32;
   const ChainStep* chain;
   const uint32_t* coef_rows;   // composition: batch x n_nodes residues (node order)
@@ -183,6 +195,8 @@ struct fpe_tree {
   // program
   std::vector<fpe::OpF64> ops64;
   std::vector<fpe::OpF32> ops32;
+  std::vector<fpe::OpF64> ops64r;       // derived by layout(): ops64 with runs (FP64, depth <= 2), else empty
+  std::vector<uint64_t> runc;           // the runs' coefficients
   std::vector<fpe::ChainStep> chain;
   std::vector<int32_t> table_var, table_deg;   // per table entry
   int32_t n_table = 0;
@@ -199,7 +213,7 @@ struct fpe_tree {
   double abs_scale = 0;
   // device image
   void* dev = nullptr;
-  size_t off_ops64 = 0, off_ops32 = 0, off_chain = 0, off_coef = 0, dev_bytes = 0;
+  size_t off_ops64 = 0, off_ops32 = 0, off_chain = 0, off_coef = 0, off_ops64r = 0, off_runc = 0, dev_bytes = 0;
 };
 
 namespace fpe {

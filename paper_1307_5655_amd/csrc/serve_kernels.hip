@@ -43,8 +43,12 @@ void k_serve_walk(WorkTable* wt) {
     for (int j = 0; j < 8; ++j) x[j] = (in && j < it.tree.nvars) ? it.pts[j][i] : 0.0;
     bool flag = false;
     if (it.domain == FPE_F64) {
-      const double y = it.tree.n_offtable == 0 ? walk_point<ArF64, DMAX, false>(it.tree, x, lds)
-                                               : walk_point<ArF64, DMAX, true>(it.tree, x, lds);
+      // the same programs as fpe_evaluate: chain-like trees walk their
+      // program with runs (the item's op pointer), the others their ops
+      double y;
+      if (it.tree.n_offtable != 0) y = walk_point<ArF64, DMAX, true>(it.tree, x, lds);
+      else if (DMAX > 2 && it.tree.depth <= 2) y = walk_point<ArF64, 2, false>(it.tree, x, lds);
+      else y = walk_point<ArF64, DMAX, false>(it.tree, x, lds);
       if (in) it.out[i] = y;
     } else {
       // the walk without on-the-fly powers (no coordinates kept) when the
@@ -114,7 +118,8 @@ ServeKernels serve_kernels() {
   k.fallback8 = (const void*)k_serve_fallback<8>;
   k.fallback16 = (const void*)k_serve_fallback<kMaxDepth>;
   k.walk_lds = std::max({walk_lds_bytes<ArF64, kMaxDepth, 1>(), walk_lds_bytes<ArDF32, kMaxDepth, 1>(),
-                         walk_lds_bytes<ArF64, 8, 1>(), walk_lds_bytes<ArDF32, 8, 1>()});
+                         walk_lds_bytes<ArF64, 8, 1>(), walk_lds_bytes<ArDF32, 8, 1>(),
+                         walk_lds_bytes<ArF64, 2, 1>(), walk_lds_bytes<ArDF32, 2, 1>()});
   k.fallback_lds = std::max(walk_lds_bytes<ArDD, 8, 1>(), walk_lds_bytes<ArDD, kMaxDepth, 1>());
   return k;
 }

@@ -636,6 +636,7 @@ struct Walker {
   using Tab = typename TabFor<Ar, table_cap<PPL>()>::T;
 
   const Op* __restrict__ ops;
+  const uint64_t* runc;   // run coefficients (plain FP64 chain walk)
   const In (*x)[8];   // x[j][var]: the coordinates of point j (kernel locals)
   Tab* tab;           // tab[j]: the power table of point j (private memory)
   RegPow<Pow> rp[PPL];   // rp[j]: entries 0..kRegPowers-1 of point j (registers)
@@ -658,7 +659,8 @@ struct Walker {
     }
   }
 
-  __device__ __forceinline__ Walker(const In (*x_)[8], Tab* t_, char* lds) : ops(nullptr), x(x_), tab(t_) {
+  __device__ __forceinline__ Walker(const In (*x_)[8], Tab* t_, char* lds)
+      : ops(nullptr), runc(nullptr), x(x_), tab(t_) {
     lt.base = (uint32_t*)lds;
     lt.col = (int)(threadIdx.x & (kWave - 1));
     if constexpr (OFFT) {
@@ -767,8 +769,56 @@ struct Walker {
   // head, right after issuing the load.
   static __device__ __forceinline__ void settle() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
+  // A run record (kRunCode): o.b steps top = top * X0 + c, the coefficients
+  // read eight at a time with scalar loads, the next eight in flight while
+  // the current ones are applied.
+  static constexpr bool kRuns = std::is_same_v<Ar, ArF64> && DMAX <= 2;
+  __device__ __forceinline__ void run_chain(const Op& o) {
+    using CW = const __attribute__((address_space(4))) uint64_t;
+    CW* __restrict__ c = (CW*)runc + o.a;
+    const int64_t K = (int64_t)o.b;
+    Pow X[PPL];
+    FPE_FOR_J { X[j] = rp[j].r[0]; }
+    auto apply = [&](const uint64_t (&cc)[8]) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const double ck = u2d(cc[k]);
+        FPE_FOR_J { m[0][j] = __builtin_fma(m[0][j], X[j], ck); }
+      }
+    };
+    int64_t i = 0;
+    if (K >= 8) {
+      uint64_t cur[8], nxt[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) cur[k] = c[k];
+      settle();
+#pragma unroll 1
+      for (; i + 16 <= K; i += 8) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) nxt[k] = c[i + 8 + k];
+        apply(cur);
+        settle();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
+      }
+      apply(cur);
+      i += 8;
+    }
+#pragma unroll 1
+    for (; i < K; ++i) {
+      const double ck = u2d(c[i]);
+      FPE_FOR_J { m[0][j] = __builtin_fma(m[0][j], X[j], ck); }
+    }
+  }
+
   // One op; true at END.
   __device__ __forceinline__ bool run_op(const Op& o) {
+    if constexpr (kRuns) {
+      if (op_code(o.deg) == kRunCode) {
+        run_chain(o);
+        return false;
+      }
+    }
     if constexpr (DMAX <= 2) {
       // chain-like walks (Hörner): almost every op is NODE_OPEN at depth 1
       // with the first register power; test it before the switch
@@ -865,6 +915,7 @@ struct Walker {
 
   __device__ __forceinline__ void run(const DevTree& tr) {
     ops = Ar::ops(tr);
+    runc = tr.runc;
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
       tab[j].build(tr, x[j], rp[j]);
