@@ -531,6 +531,42 @@ def bigpoint_phase(fpe, torch, dev, reps: int = 3):
     return res
 
 
+def few_points_phase(fpe, fpe_inputs, torch, dev, reps: int = 20):
+    """Few points, big tree: the trivariate degree-40 polynomial (12,341
+    terms; FP64 coefficients U[-1, 1] at points U[-1, 1]^3, and mod 2^61 - 1)
+    at 1 to 4096 points, by the tree walk (one lane per point) and by the
+    term-parallel path (one workgroup per point, DPP wavefront sums), with the
+    library's choice."""
+    tri = fpe_inputs.trivariate(npts=4096)
+    g = np.random.default_rng([13075655, 960])
+    res = {}
+    for name, dom in (("f64", fpe.F64), ("modp", fpe.MODP)):
+        if dom == fpe.F64:
+            t = fpe.Tree(tri.exps, g.uniform(-1, 1, len(tri.exps)), "estrin", dom).upload(dev)
+            pts = [torch.from_numpy(g.uniform(-1, 1, 4096)).to(dev) for _ in range(3)]
+        else:
+            t = fpe.Tree(tri.exps, tri.coeffs, "estrin", dom, fpe.P61).upload(dev)
+            pts = [torch.from_numpy(tri.points[j].view(np.int64).copy()).to(dev) for j in range(3)]
+        for n in (1, 16, 256, 4096):
+            sub = [p[:n].contiguous() for p in pts]
+            row = {}
+            for path in ("walk", "terms"):
+                fpe.evaluate(t, sub, path=path)
+                torch.cuda.synchronize()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                for _ in range(reps):
+                    fpe.evaluate(t, sub, path=path)
+                e1.record()
+                torch.cuda.synchronize()
+                row[f"{path}_ms"] = e0.elapsed_time(e1) / reps
+            row["speedup"] = row["walk_ms"] / row["terms_ms"]
+            row["library_choice"] = fpe.eval_path(t, n)
+            res[f"{name}_{n}"] = row
+    return res
+
+
 def compose_phase(fpe, fpe_inputs, torch, dev, reps: int = 10):
     """4096 instances of p(q(x)) mod 2^31-1, deg p = 255, deg q = 15: the time
     per call over `reps` back-to-back calls (the throughput of a stream of
@@ -832,6 +868,7 @@ def main():
     torch.cuda.empty_cache()
 
     probes = dense = served = latency = modp = compose = ival = big = modp_roof = compose_methods = bigpoint = None
+    few = None
     if not args.no_extra:
         log("rate probes")
         probes = probe_phase(torch, dev)
@@ -842,6 +879,8 @@ def main():
         log("mod-p trivariate")
         modp = modp_phase(fpe, fpe_inputs, torch, dev, hev)
         modp_roof = modp_roofline(modp, probes)
+        log("few points, big tree")
+        few = few_points_phase(fpe, fpe_inputs, torch, dev)
         log("composition")
         compose = compose_phase(fpe, fpe_inputs, torch, dev)
         log("composition by product method")
@@ -891,6 +930,7 @@ def main():
         "served": None if served is None else {"saturation": served, "poisson": latency},
         "modp_trivariate": modp,
         "modp_roofline": modp_roof,
+        "few_points_trivariate": few,
         "compose_4096": compose,
         "compose_by_product_method": compose_methods,
         "interval_1e7": ival,

@@ -185,6 +185,9 @@ typedef struct {
                                compensated walk that the fallback test compared with tol*|y|
                                (its running relative terms plus its absolute part); a point
                                not re-evaluated has |y - p(x)| <= bound_out[i] */
+  int32_t path;             /* FPE_F64 / FPE_MODP: 0 = the tree walk, 1 = the library's choice
+                               by its cost model, 2 = the term-parallel few-point path (see
+                               fpe_evaluate) */
 } fpe_eval_opts;
 
 /* Workspace needed by fpe_evaluate for npts points (0 unless FPE_F32C). */
@@ -207,11 +210,29 @@ size_t fpe_workspace_bytes(const fpe_tree* t, int64_t npts);
  *        hence p(x) for every x in the box; every bound is rounded outward.
  *        A bound that overflows is returned as [-inf, +inf].
  *   opts may be NULL for FPE_F64 / FPE_MODP / FPE_IVAL.
- * Errors: FPE_EINVAL (not uploaded, npts < 0, NULL pointers), FPE_ENOMEM
- * (workspace too small), FPE_EUNSUPPORTED (walk deeper than the kernels hold),
- * FPE_EDEVICE. */
+ * Few points, big trees (FPE_F64, FPE_MODP with 2^61 - 1): with opts->path =
+ * 2 (or 1, when the library's cost model prefers it) one workgroup per point
+ * evaluates the polynomial's terms in parallel, c * prod_j x_j^{e_j} with
+ * powers by fast exponentiation, and sums them by a wavefront reduction (DPP)
+ * and across the workgroup: the direct scheme's evaluation of the same
+ * polynomial (Section 1), exact modulo p, and in FP64 within the same
+ * 1e-13 * p~(|x|) as the walk but not bit-identical to it.  The default (0)
+ * is the tree walk.
+ * Errors: FPE_EINVAL (not uploaded, npts < 0, NULL pointers, path not 0-2),
+ * FPE_ENOMEM (workspace too small), FPE_EUNSUPPORTED (walk deeper than the
+ * kernels hold, path 2 for another domain), FPE_EDEVICE. */
 fpe_status fpe_evaluate(const fpe_tree* t, const void* const* pts, int64_t npts, void* out,
                         const fpe_eval_opts* opts, void* stream);
+
+/* The path fpe_evaluate takes with opts->path = 1 for npts points: 1 = the
+ * tree walk, 2 = the term-parallel few-point path (0 for a NULL tree).  The
+ * cost model (calibrated on MI355X): the walk runs one chain of dispatched
+ * steps per lane, about 100 ns a step in FP64 and 200 ns mod p (lanes in
+ * parallel up to ~2.6e5 points); the term path costs npts x nodes x (2 bit
+ * lengths of each variable's largest exponent + 2) operations of about 4
+ * FP64 lane-operations each (20 mod p) at 3.9e13 per second, plus 5 us; the
+ * terms are taken below half the walk's estimate. */
+int32_t fpe_eval_path(const fpe_tree* t, int64_t npts);
 
 /* Allocation-free evaluation, for callers that cannot allocate device memory
  * (code under HIP graph capture, tight serving loops, harnesses that forbid

@@ -59,7 +59,11 @@ class EvalOpts(ctypes.Structure):
                 ("flags_out", ctypes.c_void_p), ("workspace", ctypes.c_void_p),
                 ("workspace_bytes", ctypes.c_size_t), ("nfallback_out", ctypes.c_void_p),
                 ("ev_walk_begin", ctypes.c_void_p), ("ev_walk_end", ctypes.c_void_p),
-                ("bound_out", ctypes.c_void_p)]
+                ("bound_out", ctypes.c_void_p), ("path", ctypes.c_int32)]
+
+
+# fpe_eval_opts.path: the tree walk, the library's choice, the term-parallel few-point path
+PATHS = {"walk": 0, "auto": 1, "terms": 2}
 
 
 REQ_EVALUATE, REQ_COMPOSE = 0, 1
@@ -111,6 +115,7 @@ def _load():
         "fpe_compose_workspace_bytes": ([P, i32], sz),
         "fpe_compose": ([P, P, i32, P, P, sz, P], i32),
         "fpe_compose_ex_workspace_bytes": ([P, i32, i32], sz),
+        "fpe_eval_path": ([P, i64], i32),
         "fpe_compose_ex": ([P, P, i32, P, i32, P, sz, P], i32),
         "fpe_server_workspace_bytes": ([sz], sz),
         "fpe_server_create": ([P, sz, sz, i32, P, ctypes.POINTER(P)], i32),
@@ -140,7 +145,7 @@ lib = _load()
 EXPORTED = ["fpe_last_error", "fpe_version", "fpe_compile", "fpe_tree_free", "fpe_tree_nodes",
             "fpe_tree_get_info", "fpe_tree_node_exps", "fpe_tree_device_bytes", "fpe_tree_upload",
             "fpe_tree_serialize", "fpe_tree_deserialize", "fpe_workspace_bytes", "fpe_evaluate",
-            "fpe_evaluate_noalloc",
+            "fpe_evaluate_noalloc", "fpe_eval_path",
             "fpe_compose_workspace_bytes", "fpe_compose", "fpe_compose_ex_workspace_bytes", "fpe_compose_ex",
             "fpe_server_workspace_bytes", "fpe_server_create",
             "fpe_server_submit",
@@ -269,17 +274,23 @@ class Tree:
         return cls._from_handle(h)
 
 
+def eval_path(tree: Tree, npts: int) -> str:
+    """The path fpe_evaluate takes with path="auto" (fpe_eval_path): "walk" or "terms"."""
+    return {1: "walk", 2: "terms"}[int(lib.fpe_eval_path(tree.handle, npts))]
+
+
 def workspace_bytes(tree: Tree, npts: int) -> int:
     return int(lib.fpe_workspace_bytes(tree.handle, npts))
 
 
 def evaluate(tree: Tree, pts, out=None, tol: float = 1e-12, force: int = 0, cond_out=None,
              flags_out=None, workspace=None, nfallback_out=None, stream=None, events=None,
-             points_per_lane: int = 0, bound_out=None):
+             points_per_lane: int = 0, bound_out=None, path="walk"):
     """Evaluate ``tree`` at device points ``pts`` (list of tensors, one per
     variable: 1-D float64, or uint64 residues stored as int64 for FPE_MODP;
     for FPE_IVAL [npts, 2] float64 intervals (lo, hi), and the result is
-    [npts, 2] enclosures)."""
+    [npts, 2] enclosures).  ``path`` (FPE_F64 / FPE_MODP): "walk" (default),
+    "auto" (the library's cost model) or "terms" (fpe_eval_opts.path)."""
     import torch
     if tree._dev is None:
         raise FpeError(-1, "tree is not uploaded")
@@ -306,6 +317,7 @@ def evaluate(tree: Tree, pts, out=None, tol: float = 1e-12, force: int = 0, cond
         if bound_out.numel() < npts or not bound_out.is_contiguous() or bound_out.element_size() != 8:
             raise FpeError(-1, "bound_out must be a contiguous float64 tensor with a value per point")
         opts.bound_out = bound_out.data_ptr()
+    opts.path = PATHS.get(path, path)
     if events is not None:
         # raw hipEvent_t handles (ctypes.c_void_p or int)
         opts.ev_walk_begin = getattr(events[0], "value", events[0])

@@ -76,6 +76,10 @@ void layout(fpe_tree* t) {
   t->coef_rows32.clear();
   if (t->domain == FPE_MODP && t->modulus == kP31) t->coef_rows32.assign(t->coef_rows.begin(), t->coef_rows.end());
   build_runs(t);
+  // the few-point path's term coefficients (exponents: t->exps)
+  t->term_c.clear();
+  if (t->domain == FPE_F64 || (t->domain == FPE_MODP && t->modulus == kP61 && t->batch == 1))
+    for (const fpe_node& nd : t->nodes) t->term_c.push_back(nd.coef.u);
   size_t off = 0;
   // each op array is followed by kOpTail zero records (the walk reads ahead)
   t->off_ops64 = off;
@@ -90,6 +94,10 @@ void layout(fpe_tree* t) {
   if (!t->ops64r.empty()) off = align256(off + (t->ops64r.size() + kOpTail) * sizeof(OpF64));
   t->off_runc = off;
   if (!t->runc.empty()) off = align256(off + t->runc.size() * sizeof(uint64_t));
+  t->off_term_c = off;
+  if (!t->term_c.empty()) off = align256(off + t->term_c.size() * sizeof(uint64_t));
+  t->off_term_e = off;
+  if (!t->term_c.empty()) off = align256(off + t->exps.size() * sizeof(int32_t));
   t->dev_bytes = std::max<size_t>(off, 256);
 }
 }  // namespace
@@ -100,6 +108,8 @@ DevTree dev_view(const fpe_tree* t) {
   d.ops64 = (const OpF64*)(b + t->off_ops64);
   d.ops64r = t->ops64r.empty() ? d.ops64 : (const OpF64*)(b + t->off_ops64r);
   d.runc = (const uint64_t*)(b + t->off_runc);
+  d.tc = (const uint64_t*)(b + t->off_term_c);
+  d.te = (const int32_t*)(b + t->off_term_e);
   d.ops32 = (const OpF32*)(b + t->off_ops32);
   d.chain = (const ChainStep*)(b + t->off_chain);
   d.coef_rows = (const uint32_t*)(b + t->off_coef);
@@ -223,12 +233,24 @@ fpe_status fpe_tree_upload(fpe_tree* t, void* dev_buf, size_t bytes, void* strea
       e = hipMemcpyAsync(b + t->off_runc, t->runc.data(), t->runc.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
                          st);
   }
+  if (e == hipSuccess && !t->term_c.empty()) {
+    e = hipMemcpyAsync(b + t->off_term_c, t->term_c.data(), t->term_c.size() * sizeof(uint64_t),
+                       hipMemcpyHostToDevice, st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b + t->off_term_e, t->exps.data(), t->exps.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                         st);
+  }
   if (e != hipSuccess) return fail(FPE_EDEVICE, std::string("upload: ") + hipGetErrorString(e));
   t->dev = dev_buf;
   return FPE_OK;
 }
 
 size_t fpe_workspace_bytes(const fpe_tree* t, int64_t npts) { return eval_workspace_bytes(t, npts); }
+
+int32_t fpe_eval_path(const fpe_tree* t, int64_t npts) {
+  if (!t) return 0;
+  return terms_preferred(t, npts) ? 2 : 1;
+}
 
 fpe_status fpe_evaluate(const fpe_tree* t, const void* const* pts, int64_t npts, void* out,
                         const fpe_eval_opts* opts, void* stream) {

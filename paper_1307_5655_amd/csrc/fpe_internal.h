@@ -136,6 +136,8 @@ struct DevTree {
   const OpF64* ops64;
   const OpF64* ops64r;         // the FP64 chain walk's program: ops64 with runs (see kRunCode)
   const uint64_t* runc;        // FP64 bits of the runs' coefficients
+  const uint64_t* tc;          // per node: its coefficient (FP64 bits or residue; 0 for junctions)
+  const int32_t* te;           // per node: its monomial's exponents (nvars each)
   const OpF32* ops32;
   const ChainStep* chain;
   const uint32_t* coef_rows;   // composition: batch x n_nodes residues (node order)
@@ -197,6 +199,7 @@ struct fpe_tree {
   std::vector<fpe::OpF32> ops32;
   std::vector<fpe::OpF64> ops64r;       // derived by layout(): ops64 with runs (FP64, depth <= 2), else empty
   std::vector<uint64_t> runc;           // the runs' coefficients
+  std::vector<uint64_t> term_c;         // FP64 / mod 2^61-1 trees: each node's coefficient (few-point path)
   std::vector<fpe::ChainStep> chain;
   std::vector<int32_t> table_var, table_deg;   // per table entry
   int32_t n_table = 0;
@@ -214,6 +217,7 @@ struct fpe_tree {
   // device image
   void* dev = nullptr;
   size_t off_ops64 = 0, off_ops32 = 0, off_chain = 0, off_coef = 0, off_ops64r = 0, off_runc = 0, dev_bytes = 0;
+  size_t off_term_c = 0, off_term_e = 0;
 };
 
 namespace fpe {
@@ -311,6 +315,13 @@ struct KernelLaunch {
 };
 struct F32COut;
 void launch_f64(const KernelLaunch& L, double* out);
+// The few-point path (eval_terms.hip): one workgroup per point, the terms
+// over its lanes, a wavefront reduction.  domain FPE_F64 or FPE_MODP.
+void launch_terms(const KernelLaunch& L, int32_t domain, void* out);
+// Whether a tree has the few-point path's data, and whether the library takes
+// that path for npts points.
+bool terms_eligible(const fpe_tree* t);
+bool terms_preferred(const fpe_tree* t, int64_t npts);
 void launch_m61(const KernelLaunch& L, uint64_t* out);
 void launch_iv(const KernelLaunch& L, double* out);
 void launch_df32(const KernelLaunch& L, const F32COut& o);

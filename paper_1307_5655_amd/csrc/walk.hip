@@ -53,7 +53,16 @@ fpe_status launch_eval(const fpe_tree* t, const void* const* pts, int64_t npts, 
   L.stream = st;
   hipEvent_t eb = opts ? (hipEvent_t)opts->ev_walk_begin : nullptr;
   hipEvent_t ee = opts ? (hipEvent_t)opts->ev_walk_end : nullptr;
-  if (t->domain == FPE_F64) {
+  const int32_t path = opts ? opts->path : 0;
+  if (path < 0 || path > 2) return fail(FPE_EINVAL, "opts->path must be 0, 1 or 2");
+  if (path == 2 && !terms_eligible(t))
+    return fail(FPE_EUNSUPPORTED, "the term-parallel path takes FPE_F64 and FPE_MODP (2^61-1) trees");
+  if (path == 2 || (path == 1 && terms_preferred(t, npts))) {
+    if (t->domain == FPE_MODP && t->modulus != kP61) return fail(FPE_EUNSUPPORTED, "evaluation modulus must be 2^61-1");
+    if (eb) (void)hipEventRecord(eb, st);
+    launch_terms(L, t->domain, out);
+    if (ee) (void)hipEventRecord(ee, st);
+  } else if (t->domain == FPE_F64) {
     if (eb) (void)hipEventRecord(eb, st);
     launch_f64(L, (double*)out);
     if (ee) (void)hipEventRecord(ee, st);

@@ -318,3 +318,47 @@ def test_full_size_trivariate_sampled(dev):
         t = fpe.Tree(inp.exps, inp.coeffs, scheme, fpe.MODP, fpe.P61).upload(dev)
         y = fpe.evaluate(t, pts).cpu().numpy().view(np.uint64)
         assert np.array_equal(y[idx], want), scheme
+
+
+# ----------------------------------------------------------------------------
+# few points, big trees: the term-parallel path (DPP wavefront sums)
+# ----------------------------------------------------------------------------
+
+def test_term_path_few_points_big_trees(dev):
+    """One workgroup per point, terms over the lanes, wavefront reductions:
+    the trivariate degree-40 tree (12,341 terms) mod 2^61 - 1 bit-exact at 1,
+    7, 64 and 301 points (every scheme, the walk the same bits); FP64
+    multivariate trees with junctions within 1e-13 of p~ against the oracle;
+    a univariate degree-5000 tree; the cost model picks the terms for few
+    points and the walk for many; path 2 refused for the compensated form."""
+    say("term path: trivariate mod p, multivariate f64")
+    inp = fpe_inputs.trivariate(npts=301)
+    for npts in (1, 7, 64, 301):
+        pts = [to_dev(inp.points[j, :npts].copy().view(np.int64), dev) for j in range(3)]
+        want = native.modp_eval(inp.exps, inp.coeffs, fpe.P61, inp.points[:, :npts].copy())
+        for scheme in ("horner", "estrin", "balanced"):
+            t = fpe.Tree(inp.exps, inp.coeffs, scheme, fpe.MODP, fpe.P61).upload(dev)
+            for path in ("terms", "walk", "auto"):
+                y = fpe.evaluate(t, pts, path=path).cpu().numpy().view(np.uint64)
+                assert np.array_equal(y, want), (npts, scheme, path)
+    g = np.random.default_rng([13075655, 950])
+    for v, T, npts in [(3, 4000, 5), (2, 2000, 33), (4, 1500, 2)]:
+        m = fpe_inputs.random_multi_f64(v, T, npts, g)
+        ref = exact.dd_monomial_sum(m.exps, m.coeffs, m.points)
+        pt = exact.monomial_ptilde(m.exps, m.coeffs, m.points)
+        for scheme in ("horner", "balanced"):
+            t = fpe.Tree(m.exps, m.coeffs, scheme, fpe.F64).upload(dev)
+            y = fpe.evaluate(t, [to_dev(m.points[j], dev) for j in range(v)], path="terms").cpu().numpy()
+            assert (np.abs(y - ref) / pt).max() <= TOL_F64, (v, scheme)
+    inp = fpe_inputs.sparse_uni(5000, npts=3, lo=-1.05, hi=1.05)
+    e = np.nonzero(inp.coeffs)[0].astype(np.int32).reshape(-1, 1)
+    t = fpe.Tree(e, inp.coeffs[e[:, 0]], "estrin", fpe.F64).upload(dev)
+    y = fpe.evaluate(t, [to_dev(inp.points, dev)], path="terms").cpu().numpy()
+    check_f64(y, inp.coeffs, inp.points)
+    # the library's choice: terms for 16 points, the walk for 1e6
+    tri = fpe_inputs.trivariate(npts=1)
+    t3 = fpe.Tree(tri.exps, np.ones(len(tri.exps)), "estrin", fpe.F64)
+    assert fpe.eval_path(t3, 16) == "terms" and fpe.eval_path(t3, 1_000_000) == "walk"
+    tf = fpe.Tree(e, inp.coeffs[e[:, 0]], "estrin", fpe.F32C).upload(dev)
+    with pytest.raises(fpe.FpeError):
+        fpe.evaluate(tf, [to_dev(inp.points, dev)], path="terms")
