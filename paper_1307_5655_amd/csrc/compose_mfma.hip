@@ -172,6 +172,7 @@ struct GGroup {
   int32_t obase;                               // LDS byte offset of the tiles' sums
   int32_t mbase;                               // LDS byte offset of the copied records
   int32_t seg_begin[kWaves], seg_end[kWaves];  // the segments of each wavefront
+  int32_t s_begin, s_end;                      // all of the group's segments
 };
 struct GLists {
   const GGroup* groups;
@@ -253,6 +254,8 @@ __global__ __launch_bounds__(256, 3) void k_cm_mfma(GLists Ls, CBases B) {
   mp += al16((G.b_end - G.b_begin) * 4);
   int32_t* PEl = (int32_t*)mp;
   mp += al16((G.pe_end - G.pe_begin) * 4);
+  GSeg* Sl = (GSeg*)mp;
+  mp += al16((G.s_end - G.s_begin) * (int)sizeof(GSeg));
   uint32_t* Cl = (uint32_t*)mp;
   copy_words(Rl, Ls.rounds + G.rd_begin, (G.rd_end - G.rd_begin) * (int)sizeof(GRound));
   copy_words(El, Ls.ents + G.e_begin, (G.e_end - G.e_begin) * (int)sizeof(GEntry));
@@ -260,13 +263,15 @@ __global__ __launch_bounds__(256, 3) void k_cm_mfma(GLists Ls, CBases B) {
   copy_words(Ol, Ls.own + G.own_begin, kCols * (int)sizeof(GOwn));
   copy_words(Bl, Ls.bent + G.b_begin, (G.b_end - G.b_begin) * 4);
   copy_words(PEl, Ls.pent + G.pe_begin, (G.pe_end - G.pe_begin) * 4);
-  for (int j = tid; j < npar; j += blockDim.x) {
-    const int cn = Ls.pars[G.p_begin + j].coef_node;
-    Cl[j] = cn >= 0 ? B.coef[inst * B.n_nodes + cn] : 0u;
-  }
+  copy_words(Sl, Ls.segs + G.s_begin, (G.s_end - G.s_begin) * (int)sizeof(GSeg));
   uint64_t* obuf = (uint64_t*)(lds + G.obase);
   for (int i = tid; i < G.ntiles * kObufTile; i += blockDim.x) obuf[i] = 0u;
   __syncthreads();
+  // the values' constants: issued now, in flight with the staging loads
+  for (int j = tid; j < npar; j += blockDim.x) {
+    const int cn = Pl[j].coef_node;
+    Cl[j] = cn >= 0 ? B.coef[inst * B.n_nodes + cn] : 0u;
+  }
 
   for (int rl = 0; rl < G.rd_end - G.rd_begin; ++rl) {
     const GRound& R = Rl[rl];
@@ -327,7 +332,7 @@ __global__ __launch_bounds__(256, 3) void k_cm_mfma(GLists Ls, CBases B) {
   };
   int cur = -1;
   for (int sg = G.seg_begin[wave]; sg < G.seg_end[wave]; ++sg) {
-    const GSeg S = Ls.segs[sg];
+    const GSeg S = Sl[sg - G.s_begin];
     if (S.tile != cur) {
       if (cur >= 0) flush(cur);
       cur = S.tile;
@@ -480,9 +485,10 @@ std::map<RoundKey, std::vector<std::pair<int32_t, const Prod*>>> rounds_of(const
   return R;
 }
 // LDS bytes of a group's copied records.
-int32_t meta_bytes(int32_t rounds, int32_t ents, int32_t pars, int32_t bents, int32_t pents) {
+int32_t meta_bytes(int32_t rounds, int32_t ents, int32_t pars, int32_t bents, int32_t pents, int32_t segs) {
   return al16(rounds * (int)sizeof(GRound)) + al16(ents * (int)sizeof(GEntry)) + al16(pars * (int)sizeof(GParent)) +
-         al16(kCols * (int)sizeof(GOwn)) + al16(bents * 4) + al16(pents * 4) + al16(pars * 4);
+         al16(kCols * (int)sizeof(GOwn)) + al16(bents * 4) + al16(pents * 4) + al16(segs * (int)sizeof(GSeg)) +
+         al16(pars * 4);
 }
 // LDS of a group: every round's t and h planes, the tiles' sums, the records.
 size_t group_lds(const std::vector<const Value*>& vals) {
@@ -497,8 +503,10 @@ size_t group_lds(const std::vector<const Value*>& vals) {
     ne += (int32_t)kv.second.size();
     nbe += blocks;
   }
-  const int32_t np = (int32_t)vals.size();
-  return ((bytes + 15) & ~size_t(15)) + (size_t)((nb + 31) >> 5) * kObufTile * 8 + meta_bytes(nr, ne, np, nbe, nr * np);
+  const int32_t np = (int32_t)vals.size(), nt = (nb + 31) >> 5;
+  // segments: at most one per tile and round, plus one per cut between shares
+  return ((bytes + 15) & ~size_t(15)) + (size_t)nt * kObufTile * 8 +
+         meta_bytes(nr, ne, np, nbe, nr * np, nr * nt + kWaves);
 }
 
 void add_group(CSched& S, const std::vector<const Value*>& vals, Launch& L) {
@@ -578,8 +586,6 @@ void add_group(CSched& S, const std::vector<const Value*>& vals, Launch& L) {
   G.pe_end = (int32_t)S.pent.size();
   G.obase = (lds + 15) & ~15;
   G.mbase = G.obase + G.ntiles * kObufTile * 8;
-  lds = G.mbase + meta_bytes(G.rd_end - G.rd_begin, G.e_end - G.e_begin, G.p_end - G.p_begin, G.b_end - G.b_begin,
-                             G.pe_end - G.pe_begin);
   // the tiles' work, tile by tile, cut into kWaves contiguous shares of
   // (nearly) equal numbers of blocks
   int64_t total = 0;
@@ -604,6 +610,10 @@ void add_group(CSched& S, const std::vector<const Value*>& vals, Launch& L) {
       }
   G.seg_end[wv] = (int32_t)S.segs.size();
   for (int32_t k = wv + 1; k < kWaves; ++k) G.seg_begin[k] = G.seg_end[k] = (int32_t)S.segs.size();
+  G.s_begin = G.seg_begin[0];
+  G.s_end = (int32_t)S.segs.size();
+  lds = G.mbase + meta_bytes(G.rd_end - G.rd_begin, G.e_end - G.e_begin, G.p_end - G.p_begin, G.b_end - G.b_begin,
+                             G.pe_end - G.pe_begin, G.s_end - G.s_begin);
   S.groups.push_back(G);
   L.lds = std::max(L.lds, lds);
 }
