@@ -422,10 +422,12 @@ fpe_status fpe_tree_deserialize(const void* buf, size_t bytes, fpe_tree** out) {
     return fail(FPE_EINVAL, "corrupt serialised tree (power counts or node indices)");
   }
   for (int k = 0; k < 5; ++k) t->n_kind[k] = kinds[k];
-  // the FP32 records repeat the program of the FP64 ones
+  // the FP32 records repeat the program of the FP64 ones, with the dispatch
+  // codes of the double-float walk's deeper LDS tier
   bool same = t->ops32.empty() || t->ops32.size() == t->ops64.size();
   for (size_t k = 0; same && k < t->ops32.size(); ++k)
-    same = t->ops32[k].info == t->ops64[k].info && t->ops32[k].deg == t->ops64[k].deg;
+    same = t->ops32[k].info == t->ops64[k].info &&
+           t->ops32[k].deg == ((t->ops64[k].deg & 0xFFFFFu) | (dispatch_code(t->ops64[k].info, kLdsPowersF32) << 20));
   if (!same || (t->domain == FPE_F32C) != !t->ops32.empty()) {
     delete t;
     return fail(FPE_EINVAL, "corrupt serialised tree (program)");

@@ -720,7 +720,7 @@ fpe_status compile_tree(int32_t nvars, int64_t nterms, const int32_t* exps, cons
       split_f32(b, q.bh, q.bl);
       q.bk2 = bound_term_up(b);
       q.info = o.info;
-      q.deg = o.deg;
+      q.deg = (o.deg & 0xFFFFFu) | (dispatch_code(o.info, kLdsPowersF32) << 20);
       t->ops32[i] = q;
     }
   }

@@ -5,18 +5,11 @@
 namespace fpe {
 
 // COND: the condition numbers are written (o.cond); without it the walk's
-// condition sums are dead and the compiler drops them.
-// Waves per SIMD asked of the two-point depth-6 and depth-8 walks without
-// condition output: 7 and 6 instead of the 6 and 5 their registers would
-// give, for two and six spilled values on rare paths (measured 2.5-5 %
-// faster); the condition sums need the registers and keep the default.
-constexpr int df32_waves_per_eu(int dmax, int ppl, bool cond) {
-  return cond ? 1 : dmax == 6 && ppl == 2 ? 7 : dmax == 8 && ppl == 2 ? 6 : 1;
-}
-
+// condition sums are dead and the compiler drops them.  (The two-point walks
+// with the LDS tier hold 7 KB of LDS per wave, which caps them at five waves
+// per SIMD; no register budget is asked beyond that.)
 template <int DMAX, int PPL, bool OFFT, bool COND>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(df32_waves_per_eu(DMAX, PPL, COND))))
-void k_eval_df32(DevTree tr, Pts<double> P, int64_t npts, F32COut o) {
+__global__ __launch_bounds__(kBlock) void k_eval_df32(DevTree tr, Pts<double> P, int64_t npts, F32COut o) {
   extern __shared__ __align__(16) char lds[];
   const int lane = threadIdx.x & (kWave - 1);
   const int64_t base = (int64_t)blockIdx.x * kBlock * PPL + threadIdx.x;

@@ -66,18 +66,21 @@ __host__ __device__ inline uint32_t op_pidx2(uint32_t info) { return (info >> 25
 // cannot occur, so codes with L = 0 and kind 0 mark the root (END).
 constexpr int kRegPowers = 4;   // table entries kept in registers
 constexpr int kLdsPowers = 4;   // the next entries, kept in LDS (see walk_core.h)
+// The double-float walk's tier is deeper: its records (OpF32) carry dispatch
+// codes of their own, with the class boundary at entry 11.
+constexpr int kLdsPowersF32 = 7;
 enum PowClass : uint32_t { kPowMem = 4, kPowOther = 5, kPowPriv = 6 };
 constexpr uint32_t make_code(uint32_t level, uint32_t kind, uint32_t pclass) {
   return (level & 15u) | (kind << 4) | (pclass << 6);
 }
 __host__ __device__ inline uint32_t op_code(uint32_t deg) { return deg >> 20; }
 // The dispatch code of an op from its info word (whose level field holds the
-// stack depth before the op).
-__host__ __device__ inline uint32_t dispatch_code(uint32_t info) {
+// stack depth before the op), for a walk whose LDS tier holds `tier` entries.
+__host__ __device__ inline uint32_t dispatch_code(uint32_t info, int tier = kLdsPowers) {
   const uint32_t p = op_pidx(info), p2 = op_pidx2(info), kind = op_kind(info);
   uint32_t pc = kPowOther;
   if (p2 == kNoPair && p < (uint32_t)kRegPowers) pc = p;
-  else if (p2 == kNoPair && p != kOffTable) pc = p < (uint32_t)(kRegPowers + kLdsPowers) ? kPowMem : kPowPriv;
+  else if (p2 == kNoPair && p != kOffTable) pc = p < (uint32_t)(kRegPowers + tier) ? kPowMem : kPowPriv;
   if (kind == kEnd) return make_code(0, 0, (info & kEndHasPow) ? pc : kPowOther);
   const uint32_t lvl = op_level(info);
   return make_code(lvl < 15u ? lvl : 15u, kind, pc);

@@ -560,12 +560,15 @@ struct TabIV {
   __device__ __forceinline__ IV get(uint32_t i) const { return pm[i]; }
 };
 
-// LDS tier of the tables: entries kRegPowers .. kRegPowers+kLdsPowers-1 (the
-// next most used after the register copies) of every point of a wavefront,
-// stored as 32-bit planes [entry][word][point j][lane] so a wavefront reads 64
-// consecutive words (no bank conflicts).  One wavefront per workgroup, so a
-// workgroup's dynamic LDS is walk_lds_bytes<Ar, PPL>(): 4 KB for the
-// double-float walk (two-float powers) at two points per lane.  Entries beyond the tier stay in
+// LDS tier of the tables: entries kRegPowers .. kRegPowers+T-1 (the next
+// most used after the register copies; T = tier_entries<Ar>()) of every
+// point of a wavefront, stored as 32-bit planes [entry][word][point j][lane]
+// so a wavefront reads 64 consecutive words (no bank conflicts).  One
+// wavefront per workgroup, so a workgroup's dynamic LDS is
+// walk_lds_bytes<Ar, DMAX, PPL>(): 7 KB for the double-float walk (seven
+// two-float powers) at two points per lane, so that its five waves per SIMD
+// (20 per compute unit) fit in 160 KB (measured on MI355X: eight entries,
+// 8 KB, lost occupancy and ran slower than four).  Entries beyond the tier stay in
 // private memory; the tier keeps the table's hot part out of it, whose
 // working set is far beyond the caches at full occupancy.
 template <class E, int PPL>
@@ -599,9 +602,16 @@ template <class Ar, int DMAX>
 constexpr bool lds_tier() {
   return DMAX > 2;
 }
+// Entries in the tier: the double-float walk's two-float powers take half the
+// bytes of the double-double and interval ones, so it holds more (its op
+// records are coded for that).
+template <class Ar>
+constexpr int tier_entries() {
+  return std::is_same_v<Ar, ArDF32> ? kLdsPowersF32 : kLdsPowers;
+}
 template <class Ar, int DMAX, int PPL>
 constexpr size_t walk_lds_bytes() {
-  return lds_tier<Ar, DMAX>() ? (size_t)kLdsPowers * sizeof(typename Ar::Pow) * PPL * kWave : 0;
+  return lds_tier<Ar, DMAX>() ? (size_t)tier_entries<Ar>() * sizeof(typename Ar::Pow) * PPL * kWave : 0;
 }
 
 // CAP: entries a table can hold; kernels with several points per lane only
@@ -708,7 +718,7 @@ struct Walker {
   // entry i >= kRegPowers of point j's table: the LDS tier or private memory
   __device__ __forceinline__ Pow mem(int j, uint32_t i) const {
     if constexpr (lds_tier<Ar, DMAX>())
-      if (i < (uint32_t)(kRegPowers + kLdsPowers)) return lt.get(i, j);
+      if (i < (uint32_t)(kRegPowers + tier_entries<Ar>())) return lt.get(i, j);
     return tab[j].get(i);
   }
   // entry i of point j's table at full precision (for products of entries)
@@ -920,7 +930,8 @@ struct Walker {
     for (int j = 0; j < PPL; ++j) {
       tab[j].build(tr, x[j], rp[j]);
       if constexpr (lds_tier<Ar, DMAX>())
-        for (int i = kRegPowers; i < kRegPowers + kLdsPowers && i < tr.n_table; ++i) lt.put(i, j, tab[j].get(i));
+        for (int i = kRegPowers; i < kRegPowers + tier_entries<Ar>() && i < tr.n_table; ++i)
+          lt.put(i, j, tab[j].get(i));
     }
 #pragma unroll
     for (int k = 0; k < DMAX; ++k) {

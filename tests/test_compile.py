@@ -188,14 +188,15 @@ def test_serialize_roundtrip():
 def _op_arrays(blob, n):
     """Byte offsets of the FP64 and FP32 op records (n of each, 32 bytes) in a
     serialised compensated-FP32 tree: each array follows its u64 length, the
-    FP32 one right after the FP64 one, and both carry the same info and deg
-    words at bytes 16-23 of each record."""
+    FP32 one right after the FP64 one, and both carry the same info word at
+    bytes 16-19 of each record (the deg words at 20-23 differ where the
+    double-float walk's deeper LDS tier changes an entry's power class)."""
     u64 = lambda q: int.from_bytes(blob[q:q + 8], "little")
     hits = []
     for q in range(0, len(blob) - 16 - 64 * n):
         if u64(q) == n and u64(q + 8 + 32 * n) == n:
             a, b = q + 8, q + 16 + 32 * n
-            if all(blob[a + 32 * k + 16:a + 32 * k + 24] == blob[b + 32 * k + 16:b + 32 * k + 24] for k in range(n)):
+            if all(blob[a + 32 * k + 16:a + 32 * k + 20] == blob[b + 32 * k + 16:b + 32 * k + 20] for k in range(n)):
                 hits.append((a, b))
     assert len(hits) == 1
     return hits[0]
@@ -213,7 +214,12 @@ def test_deserialize_checks_the_dispatch_codes():
     a, b = _op_arrays(blob, len(t.nodes()))
     fpe.Tree.deserialize(blob)
     codes = [int.from_bytes(blob[a + 32 * k + 20:a + 32 * k + 24], "little") >> 26 for k in range(len(t.nodes()))]
+    codes32 = [int.from_bytes(blob[b + 32 * k + 20:b + 32 * k + 24], "little") >> 26 for k in range(len(t.nodes()))]
     assert {4, 6} <= set(codes)        # power classes: LDS-tier and private entries
+    # the FP64 records put entries 4-7 in the LDS tier, the FP32 ones 4-10
+    assert t.info.n_table > 11 and {4, 6} <= set(codes32)
+    moved = [k for k in range(len(codes)) if codes[k] == 6 and codes32[k] == 4]
+    assert moved and all(codes32[k] == codes[k] for k in range(len(codes)) if codes[k] != 6)
     k = codes.index(6)
     for arrays in ((a, b), (b,)):
         bad = bytearray(blob)
