@@ -531,15 +531,38 @@ def bigpoint_phase(fpe, torch, dev, reps: int = 3):
     return res
 
 
-def few_points_phase(fpe, fpe_inputs, torch, dev, reps: int = 20):
+def term_path_ops(exps) -> float:
+    """Operations the term-parallel kernel issues per point (lane divergence
+    not counted): for each term, each nonzero exponent e costs bit_length(e)
+    squarings and popcount(e) multiplications (binary exponentiation) plus
+    one multiplication into the term, and the term one addition."""
+    e = np.asarray(exps, dtype=np.int64)
+    bl = np.zeros_like(e)
+    v = e.copy()
+    while (v > 0).any():
+        bl += (v > 0)
+        v >>= 1
+    pc = np.array([[bin(int(x)).count("1") for x in row] for row in e], dtype=np.int64)
+    return float(((bl + pc + 1) * (e > 0)).sum() + len(e))
+
+
+def few_points_phase(fpe, fpe_inputs, torch, dev, reps: int = 20, probes=None):
     """Few points, big tree: the trivariate degree-40 polynomial (12,341
     terms; FP64 coefficients U[-1, 1] at points U[-1, 1]^3, and mod 2^61 - 1)
     at 1 to 4096 points, by the tree walk (one lane per point) and by the
     term-parallel path (one workgroup per point, DPP wavefront sums), with the
-    library's choice."""
+    library's choice.  The term path's roofline: its issued operations per
+    point over the launch time, against the FP64 multiply/add rate, and mod
+    2^61 - 1 against the measured rate of the modular multiply-add (each
+    modular multiplication counted as one); few points cannot fill the chip,
+    so the fraction rises with the point count."""
     tri = fpe_inputs.trivariate(npts=4096)
     g = np.random.default_rng([13075655, 960])
-    res = {}
+    ops_pt = term_path_ops(tri.exps)
+    peaks = {"f64": (FP64_FMA_PEAK, "FP64 multiplies and adds/s", "published: 39.3e12 FP64 lane-operations/s"),
+             "modp": ((probes or {}).get("m61_mac", {}).get("rate"), "mod-2^61-1 multiplications/s",
+                      "measured: the modular multiply-add in independent chains (FPE_PROBE_M61_MAC)")}
+    res = {"term_path_ops_per_point": ops_pt}
     for name, dom in (("f64", fpe.F64), ("modp", fpe.MODP)):
         if dom == fpe.F64:
             t = fpe.Tree(tri.exps, g.uniform(-1, 1, len(tri.exps)), "estrin", dom).upload(dev)
@@ -563,7 +586,15 @@ def few_points_phase(fpe, fpe_inputs, torch, dev, reps: int = 20):
                 row[f"{path}_ms"] = e0.elapsed_time(e1) / reps
             row["speedup"] = row["walk_ms"] / row["terms_ms"]
             row["library_choice"] = fpe.eval_path(t, n)
+            peak = peaks[name][0]
+            row["terms_ops_per_s"] = n * ops_pt / (row["terms_ms"] * 1e-3)
+            row["terms_frac"] = row["terms_ops_per_s"] / peak if peak else None
             res[f"{name}_{n}"] = row
+        peak, unit, src = peaks[name]
+        big = res[f"{name}_4096"]
+        res[f"roofline_{name}"] = {"kernel": f"k_eval_terms<{0 if name == 'f64' else 1}> at 4096 points",
+                                   "bound": "alu", "achieved": big["terms_ops_per_s"], "peak": peak, "unit": unit,
+                                   "peak_source": src, "frac": big["terms_frac"]}
     return res
 
 
@@ -685,6 +716,9 @@ def main():
                     help="run only the rate probes (for a profiler run of the probe kernels) and print them")
     ap.add_argument("--compose-only", action="store_true",
                     help="run only the 4096 x (255 o 15) composition (for a profiler run of its kernels) and print it")
+    ap.add_argument("--few-points-only", action="store_true",
+                    help="run only the few-point trivariate comparison (for a profiler run of the term-parallel "
+                         "and walk kernels) and print it")
     ap.add_argument("--copy-probe", type=float, default=0,
                     help="after the timed steps, copy a device buffer of this many bytes three times "
                          "(calibrates the HBM byte counters of a profiler run)")
@@ -709,6 +743,9 @@ def main():
         return
     if args.compose_only:
         print(json.dumps({"compose_4096": compose_phase(fpe, fpe_inputs, torch, dev)}), flush=True)
+        return
+    if args.few_points_only:
+        print(json.dumps({"few_points_trivariate": few_points_phase(fpe, fpe_inputs, torch, dev)}), flush=True)
         return
     degrees = (3000, 5000)
     schemes = ("balanced", "estrin", "horner")
@@ -880,7 +917,7 @@ def main():
         modp = modp_phase(fpe, fpe_inputs, torch, dev, hev)
         modp_roof = modp_roofline(modp, probes)
         log("few points, big tree")
-        few = few_points_phase(fpe, fpe_inputs, torch, dev)
+        few = few_points_phase(fpe, fpe_inputs, torch, dev, probes=probes)
         log("composition")
         compose = compose_phase(fpe, fpe_inputs, torch, dev)
         log("composition by product method")
