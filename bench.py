@@ -531,19 +531,30 @@ def bigpoint_phase(fpe, torch, dev, reps: int = 3):
     return res
 
 
+def warm_events(torch):
+    """Record and wait on one pair of torch timing events: their first use
+    sets up state on the host (tens of milliseconds), which would otherwise
+    land inside the first timed region of a phase run on its own."""
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    b.record()
+    torch.cuda.synchronize()
+    a.elapsed_time(b)
+
+
 def term_path_ops(exps) -> float:
-    """Operations the term-parallel kernel issues per point (lane divergence
-    not counted): for each term, each nonzero exponent e costs bit_length(e)
-    squarings and popcount(e) multiplications (binary exponentiation) plus
-    one multiplication into the term, and the term one addition."""
+    """Operations the term-parallel kernel issues per point: each term one
+    multiplication per variable (by its entry of the point's power table,
+    x^0 = 1 included) and one addition; the table, x_j^k for k up to the
+    largest exponent of x_j, by fast exponentiation: bit_length(k) squarings
+    and popcount(k) multiplications an entry."""
     e = np.asarray(exps, dtype=np.int64)
-    bl = np.zeros_like(e)
-    v = e.copy()
-    while (v > 0).any():
-        bl += (v > 0)
-        v >>= 1
-    pc = np.array([[bin(int(x)).count("1") for x in row] for row in e], dtype=np.int64)
-    return float(((bl + pc + 1) * (e > 0)).sum() + len(e))
+    ops = float(e.shape[0] * (e.shape[1] + 1))
+    for j in range(e.shape[1]):
+        ks = np.arange(int(e[:, j].max()) + 1)
+        ops += float(sum(int(k).bit_length() + bin(int(k)).count("1") for k in ks))
+    return ops
 
 
 def few_points_phase(fpe, fpe_inputs, torch, dev, reps: int = 20, probes=None):
@@ -556,6 +567,7 @@ def few_points_phase(fpe, fpe_inputs, torch, dev, reps: int = 20, probes=None):
     2^61 - 1 against the measured rate of the modular multiply-add (each
     modular multiplication counted as one); few points cannot fill the chip,
     so the fraction rises with the point count."""
+    warm_events(torch)
     tri = fpe_inputs.trivariate(npts=4096)
     g = np.random.default_rng([13075655, 960])
     ops_pt = term_path_ops(tri.exps)
@@ -603,6 +615,7 @@ def compose_phase(fpe, fpe_inputs, torch, dev, reps: int = 10):
     per call over `reps` back-to-back calls (the throughput of a stream of
     batches), and the median time of single calls with the device idle
     before each (latency, including the schedule's upload and the launches)."""
+    warm_events(torch)
     inp = fpe_inputs.compose_batch()
     b, dp1 = inp.p.shape
     ex = np.arange(dp1, dtype=np.int32).reshape(-1, 1)

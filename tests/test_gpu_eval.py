@@ -329,8 +329,12 @@ def test_term_path_few_points_big_trees(dev):
     the trivariate degree-40 tree (12,341 terms) mod 2^61 - 1 bit-exact at 1,
     7, 64 and 301 points (every scheme, the walk the same bits); FP64
     multivariate trees with junctions within 1e-13 of p~ against the oracle;
-    a univariate degree-5000 tree; the cost model picks the terms for few
-    points and the walk for many; path 2 refused for the compensated form."""
+    univariate degree-5000 and degree-9000 trees (the point's power table in
+    LDS, and too large for it); mod 2^61 - 1 at the table's limit (8,000
+    entries: degree 7,999 with the table, 8,000 without); four points per
+    workgroup from 2,048 points, the same bits as one; the cost model
+    picks the terms for few points and the walk for many; path 2 refused for
+    the compensated form."""
     say("term path: trivariate mod p, multivariate f64")
     inp = fpe_inputs.trivariate(npts=301)
     for npts in (1, 7, 64, 301):
@@ -350,11 +354,40 @@ def test_term_path_few_points_big_trees(dev):
             t = fpe.Tree(m.exps, m.coeffs, scheme, fpe.F64).upload(dev)
             y = fpe.evaluate(t, [to_dev(m.points[j], dev) for j in range(v)], path="terms").cpu().numpy()
             assert (np.abs(y - ref) / pt).max() <= TOL_F64, (v, scheme)
-    inp = fpe_inputs.sparse_uni(5000, npts=3, lo=-1.05, hi=1.05)
-    e = np.nonzero(inp.coeffs)[0].astype(np.int32).reshape(-1, 1)
-    t = fpe.Tree(e, inp.coeffs[e[:, 0]], "estrin", fpe.F64).upload(dev)
-    y = fpe.evaluate(t, [to_dev(inp.points, dev)], path="terms").cpu().numpy()
-    check_f64(y, inp.coeffs, inp.points)
+    for n in (9000, 5000):
+        inp = fpe_inputs.sparse_uni(n, npts=3, lo=-1.05, hi=1.05)
+        e = np.nonzero(inp.coeffs)[0].astype(np.int32).reshape(-1, 1)
+        t = fpe.Tree(e, inp.coeffs[e[:, 0]], "estrin", fpe.F64).upload(dev)
+        y = fpe.evaluate(t, [to_dev(inp.points, dev)], path="terms").cpu().numpy()
+        check_f64(y, inp.coeffs, inp.points)
+    g2 = np.random.default_rng([13075655, 951])
+    for dmax in (7999, 8000):
+        ex = np.unique(np.concatenate([g2.integers(0, dmax, 400), [dmax]])).astype(np.int32).reshape(-1, 1)
+        co = g2.integers(0, int(fpe.P61), len(ex), dtype=np.uint64)
+        x = g2.integers(0, int(fpe.P61), (1, 5), dtype=np.uint64)
+        want = native.modp_eval(ex, co, fpe.P61, x)
+        tm = fpe.Tree(ex, co, "balanced", fpe.MODP, fpe.P61).upload(dev)
+        y = fpe.evaluate(tm, [to_dev(x[0].copy().view(np.int64), dev)], path="terms").cpu().numpy().view(np.uint64)
+        assert np.array_equal(y, want), dmax
+    # from 2,048 points a workgroup takes four (ragged tail of three): mod p
+    # bit-exact, FP64 the same bits as one point per workgroup and within
+    # tolerance of the oracle
+    say("term path: four points per workgroup")
+    inp = fpe_inputs.trivariate(npts=2051)
+    want = native.modp_eval(inp.exps, inp.coeffs, fpe.P61, inp.points.copy())
+    t = fpe.Tree(inp.exps, inp.coeffs, "estrin", fpe.MODP, fpe.P61).upload(dev)
+    y = fpe.evaluate(t, [to_dev(inp.points[j].copy().view(np.int64), dev) for j in range(3)],
+                     path="terms").cpu().numpy().view(np.uint64)
+    assert np.array_equal(y, want)
+    m = fpe_inputs.random_multi_f64(3, 3000, 2051, np.random.default_rng([13075655, 952]))
+    t = fpe.Tree(m.exps, m.coeffs, "balanced", fpe.F64).upload(dev)
+    xs = [to_dev(m.points[j], dev) for j in range(3)]
+    y4 = fpe.evaluate(t, xs, path="terms").cpu().numpy()
+    y1 = fpe.evaluate(t, [x[:301].contiguous() for x in xs], path="terms").cpu().numpy()
+    assert np.array_equal(y4[:301].view(np.uint64), y1.view(np.uint64))
+    ref = exact.dd_monomial_sum(m.exps, m.coeffs, m.points)
+    pt = exact.monomial_ptilde(m.exps, m.coeffs, m.points)
+    assert (np.abs(y4 - ref) / pt).max() <= TOL_F64
     # the library's choice: terms for 16 points, the walk for 1e6
     tri = fpe_inputs.trivariate(npts=1)
     t3 = fpe.Tree(tri.exps, np.ones(len(tri.exps)), "estrin", fpe.F64)
