@@ -354,12 +354,13 @@ fpe_status fpe_compose(const fpe_tree* t, const uint32_t* q, int32_t dq, uint32_
  * use fit the HBM budget and an in-flight slot is free.  Admitted FPE_F64 /
  * FPE_F32C evaluate requests are packed into one fused launch (a work table
  * of (tree, point range) blocks) replayed through a HIP graph; FPE_MODP
- * evaluate and compose requests of the batch run beside it as their own
- * launches.  Each batch runs on one of two streams of the server (default
+ * evaluate requests, FPE_F64 requests that take the term-parallel path (few
+ * points on big trees: request path 2, or 1 where the cost model picks it)
+ * and compose requests of the batch run beside it as their own launches.  Each batch runs on one of two streams of the server (default
  * priority), so a batch overlaps the tail of the one before it; requests
  * arriving while batches run join the next one.  Each point's result depends
  * only on its own walk, so a request's output is the same bits alone
- * (fpe_evaluate / fpe_compose) and in any mix.  Latency is measured from
+ * (fpe_evaluate with the request's path / fpe_compose) and in any mix.  Latency is measured from
  * submit to the host observing completion.
  *
  * Device memory: the server takes one caller-owned device buffer (for
@@ -388,6 +389,10 @@ typedef struct {
   int32_t kind;             /* fpe_request_kind */
   const uint32_t* q;        /* compose: device uint32[batch * (dq + 1)] */
   int32_t dq;               /* compose: degree of q (>= 1) */
+  int32_t path;             /* evaluate, FPE_F64 / FPE_MODP: as fpe_eval_opts.path (0 = the tree
+                               walk, 1 = the cost model's choice, 2 = the term-parallel path);
+                               0 for FPE_F32C.  A request on the term path runs as its own
+                               launch beside the fused walk. */
 } fpe_request;
 
 typedef struct {

@@ -73,7 +73,8 @@ class Request(ctypes.Structure):
     _fields_ = [("tree", ctypes.c_void_p), ("pts", ctypes.c_void_p * 8), ("npts", ctypes.c_int64),
                 ("out", ctypes.c_void_p), ("cond_out", ctypes.c_void_p), ("tol", ctypes.c_double),
                 ("domain", ctypes.c_int32), ("kind", ctypes.c_int32), ("q", ctypes.c_void_p),
-                ("dq", ctypes.c_int32)]
+                ("dq", ctypes.c_int32),
+                ("path", ctypes.c_int32)]
 
 
 class Stats(ctypes.Structure):
@@ -476,9 +477,10 @@ class Server:
                                      _stream_ptr(stream), ctypes.byref(h)))
         self._h = h
 
-    def submit(self, tree: Tree, pts, out, domain=F32C, tol=1e-12, cond_out=None) -> int:
+    def submit(self, tree: Tree, pts, out, domain=F32C, tol=1e-12, cond_out=None, path="walk") -> int:
         """An evaluate request: FPE_F64 / FPE_F32C (float64 points and output)
-        or FPE_MODP (residues as int64 tensors)."""
+        or FPE_MODP (residues as int64 tensors); ``path`` as in evaluate()
+        (FPE_F64 / FPE_MODP)."""
         n = pts[0].numel()
         if len(pts) != tree.nvars or any(p.numel() != n or not p.is_contiguous() or p.element_size() != 8
                                          for p in pts) \
@@ -495,6 +497,7 @@ class Server:
         r.tol = tol
         r.domain = domain
         r.kind = REQ_EVALUATE
+        r.path = PATHS.get(path, path)
         t = ctypes.c_uint64()
         _check(lib.fpe_server_submit(self._h, ctypes.byref(r), ctypes.byref(t)))
         return t.value

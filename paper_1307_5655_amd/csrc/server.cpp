@@ -10,8 +10,9 @@
 // per table, replayed from a HIP graph whose nodes are
 //   copy host table -> device, zero the fallback counters, fused walk,
 //   fused FP64 fallback, copy counters device -> host;
-// mod-p evaluate and compose requests of the same batch run as their own
-// launches after the graphs.  A graph is built once per slot and table and
+// mod-p evaluate requests, FP64 requests on the term-parallel path and
+// compose requests of the same batch run as their own launches after the
+// graphs.  A graph is built once per slot and table and
 // replayed unchanged: a batch is described entirely by the work table it
 // copies in.  The two batch slots have a stream each (default priority), so
 // the next batch is admitted, staged and launched while the previous one
@@ -143,7 +144,7 @@ struct Slot {
   hipEvent_t done_ev = nullptr;
   bool busy = false;
   std::vector<Req> reqs[2];        // the fused requests of each table, in table order
-  std::vector<Req> others;         // mod-p evaluate and compose requests
+  std::vector<Req> others;         // mod-p evaluate, FP64 term-path and compose requests
   double busy_start = 0;
 };
 
@@ -198,8 +199,12 @@ size_t req_bytes(const fpe_request& r) {
   }
   return b;
 }
+// Requests of the fused walk: compensated FP32, and FP64 on the tree walk
+// (path 0, or 1 where the cost model keeps the walk).
 bool fused(const fpe_request& r) {
-  return r.kind == FPE_REQ_EVALUATE && (r.domain == FPE_F64 || r.domain == FPE_F32C);
+  if (r.kind != FPE_REQ_EVALUATE) return false;
+  if (r.domain == FPE_F32C) return true;
+  return r.domain == FPE_F64 && (r.path == 0 || (r.path == 1 && !terms_preferred(r.tree, r.npts)));
 }
 
 fpe_status build_slot(fpe_server* s, Slot& sl, char* tables) {
@@ -329,8 +334,11 @@ bool try_launch(fpe_server* s, Slot& sl) {
     if (q.r.kind == FPE_REQ_COMPOSE)
       st = launch_compose(q.r.tree, q.r.q, q.r.dq, (uint32_t*)q.r.out, s->pool_dev + q.ws_off, q.ws_bytes,
                           sl.stream);
-    else
-      st = launch_eval(q.r.tree, q.r.pts, q.r.npts, q.r.out, nullptr, sl.stream);
+    else {
+      fpe_eval_opts eo{};
+      eo.path = q.r.path;
+      st = launch_eval(q.r.tree, q.r.pts, q.r.npts, q.r.out, &eo, sl.stream);
+    }
     ok = st == FPE_OK;
   }
   if (!ok || hipEventRecord(sl.done_ev, sl.stream) != hipSuccess) s->dev_err = "server: batch launch failed";
@@ -491,6 +499,10 @@ fpe_status fpe_server_submit(fpe_server* s, const fpe_request* r, uint64_t* tick
     if (!r->out && r->npts > 0) return fail(FPE_EINVAL, "NULL output array");
     for (int j = 0; j < t->nvars; ++j)
       if (r->npts > 0 && !r->pts[j]) return fail(FPE_EINVAL, "NULL point array");
+    if (r->path < 0 || r->path > 2 || (r->domain == FPE_F32C && r->path != 0))
+      return fail(FPE_EINVAL, "request path must be 0, 1 or 2 (0 for FPE_F32C)");
+    if (r->path == 2 && !terms_eligible(t))
+      return fail(FPE_EUNSUPPORTED, "the term-parallel path takes FPE_F64 and FPE_MODP (2^61-1) trees");
   } else {
     return fail(FPE_EINVAL, "unknown request kind");
   }

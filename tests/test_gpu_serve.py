@@ -182,6 +182,56 @@ def test_serve_modp_and_compose_requests_in_the_mix(dev):
     srv.close()
 
 
+def test_serve_term_path_requests(dev):
+    """Few points on a big tree: FP64 and mod 2^61 - 1 requests on the
+    term-parallel path (path "terms", and "auto" where the cost model picks
+    it) join the batches beside fused walks; each result is the same bits as
+    fpe_evaluate with that path (mod p also the oracle's); a path on a
+    compensated request is refused."""
+    say("serve: term-path requests in the mix")
+    from oracle import native
+    tri = fpe_inputs.trivariate(npts=64)
+    g = np.random.default_rng([13075655, 930])
+    tf = fpe.Tree(tri.exps, g.uniform(-1, 1, len(tri.exps)), "estrin", fpe.F64).upload(dev)
+    tm = fpe.Tree(tri.exps, tri.coeffs, "balanced", fpe.MODP, fpe.P61).upload(dev)
+    xf = [torch.from_numpy(g.uniform(-1, 1, 64)).to(dev) for _ in range(3)]
+    xm = [torch.from_numpy(tri.points[j].copy().view(np.int64)).to(dev) for j in range(3)]
+    fl = prepare(make_requests(6, 11, max_terms=800, max_pts=20_000), dev)
+    torch.cuda.synchronize()
+    srv = fpe.Server(hbm_budget=256 << 20, max_inflight=32)
+    outs = []
+    for i, (t, dom, pts, m) in enumerate(fl):
+        o = torch.full((pts[0].numel(),), np.nan, dtype=torch.float64, device=dev)
+        outs.append(("f", t, pts, "walk", o, srv.submit(t, pts, o, domain=dom)))
+        n = (1, 16, 64)[i % 3]
+        for path in ("terms", "auto"):
+            assert fpe.eval_path(tf, n) == "terms" and fpe.eval_path(tm, n) == "terms"
+            sub = [x[:n].contiguous() for x in xf]
+            o = torch.full((n,), np.nan, dtype=torch.float64, device=dev)
+            outs.append(("x", tf, sub, path, o, srv.submit(tf, sub, o, domain=fpe.F64, path=path)))
+            subm = [x[:n].contiguous() for x in xm]
+            om = torch.full((n,), -1, dtype=torch.int64, device=dev)
+            outs.append(("m", tm, subm, path, om, srv.submit(tm, subm, om, domain=fpe.MODP, path=path)))
+    srv.drain()
+    for kind, t, pts, path, o, tk in outs:
+        assert srv.poll(tk)
+        got = o.cpu().numpy()
+        assert np.array_equal(got.view(np.uint64), fpe.evaluate(t, pts, path=path).cpu().numpy().view(np.uint64)) \
+            if kind != "f" else np.array_equal(got, fpe.evaluate(t, pts).cpu().numpy()), (kind, path)
+        if kind == "m":
+            n = pts[0].numel()
+            assert np.array_equal(got.view(np.uint64), native.modp_eval(tri.exps, tri.coeffs, fpe.P61,
+                                                                        tri.points[:, :n].copy()))
+    st = srv.stats()
+    assert st.completed == st.submitted == len(outs) and st.hbm_in_use == 0
+    t, dom, pts, m = fl[0]
+    tc = fpe.Tree(m.exps, m.coeffs, "estrin", fpe.F32C).upload(dev)
+    with pytest.raises(fpe.FpeError):
+        srv.submit(tc, pts, torch.empty(pts[0].numel(), dtype=torch.float64, device=dev), domain=fpe.F32C,
+                   path="terms")
+    srv.close()
+
+
 def test_serve_requests_arriving_during_a_batch(dev):
     say("serve: requests arriving while others run")
     reqs = prepare(make_requests(60, 4, max_terms=2000, max_pts=100_000), dev)
