@@ -55,6 +55,56 @@ struct BigArgs {
 constexpr int kBigStage = 3072;
 constexpr int kBigCols = 4096;
 
+// Carry, 64 columns at a time (lane l: column base + l), as a carry-lookahead
+// over the wavefront.  Column k's 64-bit sum is four 16-bit digits, digit i
+// weighing 2^16 in column k + i, so the digit sum D of a column (digit i of
+// column k - i) is below 2^18; its bits above 16 (at most 3) move up one
+// column, leaving E = (D mod 2^16) + (D of column k - 1) / 2^16 < 2^16 + 3,
+// whose carry out is at most 1: generated where E > 0xFFFF, propagated where
+// E = 0xFFFF.  With G and P those lanes' ballots, (G | P) + G + c_in is a
+// binary sum whose carry into bit l is exactly column l's carry in.  Columns
+// nhi .. nhi + 2 take the top digits of the last three: anything left there
+// is an overflow (the value needs more than lout limbs).  Writes the nhi
+// limbs of out and returns the result's length (highest nonzero limb + 1,
+// at least 1) in every lane.  Col reads a column from LDS or global memory
+// by its own kind of load (a generic pointer would take flat loads, whose
+// aperture is chosen from the base address, which may lie below the column
+// array when the compiler folds an offset into the load).
+template <class Col>
+__device__ __forceinline__ int carry_pass(int nhi, uint32_t* out, int32_t* overflow, Col col_at) {
+  const int lane = threadIdx.x;
+  uint32_t cin = 0, hprev = 0;
+  int lenv = 1;
+  bool ovf = false;
+  const int ncol = nhi + 3;
+  for (int base = 0; base < ncol; base += kLanes) {
+    const int k = base + lane;
+    uint32_t D = 0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int kk = k - i;
+      if (kk >= 0 && kk < nhi) D += (uint32_t)((col_at(kk) >> (16 * i)) & 0xFFFFu);
+    }
+    const uint32_t lo = D & 0xFFFFu, hi = D >> 16;
+    uint32_t hb = (uint32_t)__shfl_up((int)hi, 1);
+    if (lane == 0) hb = hprev;
+    const uint32_t E = lo + hb;
+    const uint64_t G = __ballot(E > 0xFFFFu), Pm = __ballot(E == 0xFFFFu);
+    const uint64_t Am = G | Pm;
+    const uint64_t cm = (Am + G + cin) ^ Am ^ G;   // bit l: carry into column base + l
+    const uint32_t limb = (E + (uint32_t)((cm >> lane) & 1u)) & 0xFFFFu;
+    if (k < nhi) out[k] = limb;
+    else if (limb) ovf = true;
+    const uint64_t nz = __ballot(k < nhi && limb != 0);
+    if (nz) lenv = base + 64 - __clzll((long long)nz);
+    cin = (uint32_t)(((G >> 63) | ((Pm >> 63) & (cm >> 63))) & 1u);
+    hprev = (uint32_t)__shfl((int)hi, kLanes - 1);
+  }
+  if (cin || hprev) ovf = true;
+  if (ovf) *overflow = 1;
+  return lenv;
+}
+
 // out (+)= a[0 .. la) * b[0 .. lb) + c0, where out holds lacc limbs when
 // accumulating; returns the length of the result (index of the highest
 // nonzero limb + 1, at least 1).  Only the limbs below the result's length
@@ -78,7 +128,7 @@ __device__ int big_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uin
   __syncthreads();
   const uint32_t* A = stage_a ? sa : a;
   const uint32_t* Bv = stage_b ? sb : b;
-  uint64_t* C = nhi <= kBigCols ? scol : col;
+  const bool lds_cols = nhi <= kBigCols;
   for (int k = lane; k < nhi; k += kLanes) {
     uint64_t s = 0;
     if (k < lp) {
@@ -87,37 +137,14 @@ __device__ int big_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uin
     }
     if (accumulate && k < lacc) s += out[k];
     if (k < 4) s += (c0 >> (16 * k)) & 0xFFFFu;
-    C[k] = s;
+    if (lds_cols) scol[k] = s;
+    else col[k] = s;
   }
   __syncthreads();
-  if (lane == 0) {
-    // columns are read eight at a time so their loads overlap
-    uint64_t carry = 0;
-    int len = 1;
-    int k = 0;
-    for (; k + 8 <= nhi; k += 8) {
-      uint64_t v[8];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = C[k + u];
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        carry += v[u];
-        const uint32_t limb = (uint32_t)(carry & 0xFFFFu);
-        out[k + u] = limb;
-        if (limb) len = k + u + 1;
-        carry >>= 16;
-      }
-    }
-    for (; k < nhi; ++k) {
-      carry += C[k];
-      const uint32_t limb = (uint32_t)(carry & 0xFFFFu);
-      out[k] = limb;
-      if (limb) len = k + 1;
-      carry >>= 16;
-    }
-    if (carry) *overflow = 1;
-    len_s = len;
-  }
+  int n;
+  if (lds_cols) n = carry_pass(nhi, out, overflow, [&](int kk) { return scol[kk]; });
+  else n = carry_pass(nhi, out, overflow, [&](int kk) { return col[kk]; });
+  if (lane == 0) len_s = n;
   __syncthreads();
   return len_s;
 }

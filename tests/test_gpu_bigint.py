@@ -61,6 +61,20 @@ def test_bigint_degree_255_batch(dev, scheme):
     check(got, exps, cs, xs)
 
 
+@pytest.mark.parametrize("scheme", ["horner", "balanced"])
+def test_bigint_carry_chains(dev, scheme):
+    """All-ones coefficients and points (2^64 - 1, 2^k - 1, 2^k) make the
+    product columns' sums carry through long runs of 0xFFFF limbs, across
+    the 64-column passes of the carry; values of several hundred limbs."""
+    say(f"bigint carry chains, {scheme}")
+    n = 40
+    exps = list(range(n + 1))
+    cs = [2 ** 64 - 1] * (n + 1)
+    xs = [2 ** 256 - 1, 2 ** 255, 2 ** 200 - 1, 2 ** 64 - 1, 2 ** 128 + 2 ** 64 - 1, 1, 0, 3]
+    got, t = run(exps, cs, scheme, xs, 16, dev)
+    check(got, exps, cs, xs)
+
+
 def test_bigint_errors(dev):
     say("bigint errors")
     t = fpe.Tree(np.array([[0], [5]], dtype=np.int32), np.array([3, 4], dtype=np.uint64), "horner",
