@@ -126,19 +126,28 @@ __device__ int big_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uin
   if (stage_b)
     for (int k = lane; k < lb; k += kLanes) sb[k] = b[k];
   __syncthreads();
-  const uint32_t* A = stage_a ? sa : a;
-  const uint32_t* Bv = stage_b ? sb : b;
   const bool lds_cols = nhi <= kBigCols;
-  for (int k = lane; k < nhi; k += kLanes) {
-    uint64_t s = 0;
-    if (k < lp) {
-      const int i0 = max(0, k - (lb - 1)), i1 = min(la - 1, k);
-      for (int i = i0; i <= i1; ++i) s += (uint64_t)A[i] * Bv[k - i];
+  // the column sums; both operands staged (the common case) read LDS by LDS
+  // loads, otherwise each from where it lives
+  auto columns = [&](auto rd_a, auto rd_b) {
+    for (int k = lane; k < nhi; k += kLanes) {
+      uint64_t s = 0;
+      if (k < lp) {
+        const int i0 = max(0, k - (lb - 1)), i1 = min(la - 1, k);
+        for (int i = i0; i <= i1; ++i) s += (uint64_t)rd_a(i) * rd_b(k - i);
+      }
+      if (accumulate && k < lacc) s += out[k];
+      if (k < 4) s += (c0 >> (16 * k)) & 0xFFFFu;
+      if (lds_cols) scol[k] = s;
+      else col[k] = s;
     }
-    if (accumulate && k < lacc) s += out[k];
-    if (k < 4) s += (c0 >> (16 * k)) & 0xFFFFu;
-    if (lds_cols) scol[k] = s;
-    else col[k] = s;
+  };
+  if (stage_a && stage_b) {
+    columns([&](int i) { return sa[i]; }, [&](int i) { return sb[i]; });
+  } else {
+    const uint32_t* A = stage_a ? sa : a;
+    const uint32_t* Bv = stage_b ? sb : b;
+    columns([&](int i) { return A[i]; }, [&](int i) { return Bv[i]; });
   }
   __syncthreads();
   int n;
