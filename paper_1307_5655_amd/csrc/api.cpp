@@ -15,48 +15,84 @@ const char* last_error();
 namespace {
 inline size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
-// The plain FP64 walk's program for chain-like trees (depth <= 2, every power
-// in the table): maximal sequences of at least kRunMinOps depth-1 NODE_OPEN
-// steps by powers of the first table entry become run records (kRunCode).
-// Other trees keep ops64.
+// The chain walk's program for chain-like trees (depth <= 2, every power in
+// the table), FP64 and double-float: maximal sequences of at least
+// kRunMinOps depth-1 NODE_OPEN steps by powers of the first table entry
+// become run records (kRunCode).  Other trees keep their ops.
 void build_runs(fpe_tree* t) {
   t->ops64r.clear();
+  t->ops32r.clear();
   t->runc.clear();
-  if (t->domain != FPE_F64 || t->depth > 2 || t->n_offtable > 0 || t->n_table < 1 || t->table_deg[0] <= 0) return;
+  const bool f32 = t->domain == FPE_F32C;
+  if ((t->domain != FPE_F64 && !f32) || t->depth > 2 || t->n_offtable > 0 || t->n_table < 1 ||
+      t->table_deg[0] <= 0 || (f32 && t->ops32.size() != t->ops64.size()))
+    return;
   const int32_t v0 = t->table_var[0], d0 = t->table_deg[0];
+  const int max_gap = f32 ? kRunMaxGapF32 : kRunMaxGap;
   auto unit_steps = [&](const OpF64& o) -> int {   // steps of x^d0 the op is; 0: not a chain step
     if (op_kind(o.info) != kNodeOpen || op_level(o.info) != 1 || op_pidx2(o.info) != kNoPair) return 0;
     const uint32_t p = op_pidx(o.info);
     if (p == kOffTable || (int32_t)p >= t->n_table || t->table_var[p] != v0 || t->table_deg[p] % d0) return 0;
     const int k = t->table_deg[p] / d0;
-    return k <= kRunMaxGap ? k : 0;
+    return k <= max_gap ? k : 0;
+  };
+  auto word2 = [](float a, float b) {
+    uint32_t ua, ub;
+    std::memcpy(&ua, &a, 4);
+    std::memcpy(&ub, &b, 4);
+    return (uint64_t)ua | ((uint64_t)ub << 32);
+  };
+  auto bits32 = [](uint32_t v) {
+    float f;
+    std::memcpy(&f, &v, 4);
+    return f;
   };
   const size_t n = t->ops64.size();
   std::vector<OpF64> prog;
+  std::vector<OpF32> prog32;
   std::vector<uint64_t> coefs;
   bool any = false;
   for (size_t i = 0; i < n;) {
     size_t j = i;
     while (j < n && unit_steps(t->ops64[j]) > 0) ++j;
     if (j - i >= (size_t)kRunMinOps) {
-      OpF64 r = t->ops64[i];
-      r.a = coefs.size();
-      for (size_t k = i; k < j; ++k) {
-        for (int z = 1; z < unit_steps(t->ops64[k]); ++z) coefs.push_back(0);   // +0.0
-        coefs.push_back(t->ops64[k].b);
+      if (f32) {
+        OpF32 r = t->ops32[i];
+        const size_t first = coefs.size() / kRunWordsF32;
+        for (size_t k = i; k < j; ++k) {
+          for (int z = 1; z < unit_steps(t->ops64[k]); ++z) {   // b = 0, no bound term
+            coefs.push_back(0);
+            coefs.push_back(0);
+          }
+          coefs.push_back(word2(t->ops32[k].bh, t->ops32[k].bl));
+          coefs.push_back(word2(t->ops32[k].bk2, 0.f));
+        }
+        r.ah = bits32((uint32_t)first);
+        r.al = bits32((uint32_t)(coefs.size() / kRunWordsF32 - first));
+        r.deg = kRunCode << 20;
+        prog32.push_back(r);
+      } else {
+        OpF64 r = t->ops64[i];
+        r.a = coefs.size();
+        for (size_t k = i; k < j; ++k) {
+          for (int z = 1; z < unit_steps(t->ops64[k]); ++z) coefs.push_back(0);   // +0.0
+          coefs.push_back(t->ops64[k].b);
+        }
+        r.b = coefs.size() - r.a;
+        r.deg = kRunCode << 20;
+        prog.push_back(r);
       }
-      r.b = coefs.size() - r.a;
-      r.deg = kRunCode << 20;
-      prog.push_back(r);
       any = true;
       i = j;
     } else {
-      prog.push_back(t->ops64[i]);
+      if (f32) prog32.push_back(t->ops32[i]);
+      else prog.push_back(t->ops64[i]);
       ++i;
     }
   }
-  if (!any) return;
-  t->ops64r = std::move(prog);
+  if (!any || coefs.size() / 2 > 0x7fffffffu) return;
+  if (f32) t->ops32r = std::move(prog32);
+  else t->ops64r = std::move(prog);
   t->runc = std::move(coefs);
 }
 
@@ -92,6 +128,8 @@ void layout(fpe_tree* t) {
   if (t->domain == FPE_MODP && t->modulus == kP31) off = align256(off + t->coef_rows.size() * sizeof(uint32_t));
   t->off_ops64r = off;
   if (!t->ops64r.empty()) off = align256(off + (t->ops64r.size() + kOpTail) * sizeof(OpF64));
+  t->off_ops32r = off;
+  if (!t->ops32r.empty()) off = align256(off + (t->ops32r.size() + kOpTail) * sizeof(OpF32));
   t->off_runc = off;
   if (!t->runc.empty()) off = align256(off + t->runc.size() * sizeof(uint64_t));
   t->off_term_c = off;
@@ -107,6 +145,7 @@ DevTree dev_view(const fpe_tree* t) {
   const char* b = (const char*)t->dev;
   d.ops64 = (const OpF64*)(b + t->off_ops64);
   d.ops64r = t->ops64r.empty() ? d.ops64 : (const OpF64*)(b + t->off_ops64r);
+  d.ops32r = t->ops32r.empty() ? (const OpF32*)(b + t->off_ops32) : (const OpF32*)(b + t->off_ops32r);
   d.runc = (const uint64_t*)(b + t->off_runc);
   d.tc = (const uint64_t*)(b + t->off_term_c);
   d.te = (const int32_t*)(b + t->off_term_e);
@@ -229,10 +268,16 @@ fpe_status fpe_tree_upload(fpe_tree* t, void* dev_buf, size_t bytes, void* strea
     if (e == hipSuccess)
       e = hipMemcpyAsync(b + t->off_ops64r + t->ops64r.size() * sizeof(OpF64), kZero64, sizeof kZero64,
                          hipMemcpyHostToDevice, st);
-    if (e == hipSuccess)
-      e = hipMemcpyAsync(b + t->off_runc, t->runc.data(), t->runc.size() * sizeof(uint64_t), hipMemcpyHostToDevice,
-                         st);
   }
+  if (e == hipSuccess && !t->ops32r.empty()) {
+    e = hipMemcpyAsync(b + t->off_ops32r, t->ops32r.data(), t->ops32r.size() * sizeof(OpF32), hipMemcpyHostToDevice,
+                       st);
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(b + t->off_ops32r + t->ops32r.size() * sizeof(OpF32), kZero32, sizeof kZero32,
+                         hipMemcpyHostToDevice, st);
+  }
+  if (e == hipSuccess && !t->runc.empty())
+    e = hipMemcpyAsync(b + t->off_runc, t->runc.data(), t->runc.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !t->term_c.empty()) {
     e = hipMemcpyAsync(b + t->off_term_c, t->term_c.data(), t->term_c.size() * sizeof(uint64_t),
                        hipMemcpyHostToDevice, st);

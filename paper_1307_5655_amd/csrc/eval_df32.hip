@@ -86,10 +86,15 @@ static void go(const KernelLaunch& L, const F32COut& o) {
 
 void launch_df32(const KernelLaunch& L, const F32COut& o) {
   const bool d2 = L.tr.depth <= 2, d6 = L.tr.depth <= 6, d8 = L.tr.depth <= 8;
+  // the chain-like kernels read the program with runs (both widths, so the
+  // bits do not depend on the points per lane)
+  KernelLaunch R = L;
+  R.tr.ops32 = L.tr.ops32r;
   if (L.offt) {
     if (d8) go<8, 1, true>(L, o); else go<kMaxDepth, 1, true>(L, o);
-  } else if (L.ppl >= 2 && d2) {
-    go<2, 2, false>(L, o);
+  } else if (d2) {
+    if (L.ppl >= 2) go<2, 2, false>(R, o);
+    else go<2, 1, false>(R, o);
   } else if (L.ppl >= 2 && d6) {
     go<6, 2, false>(L, o);
   } else if (L.ppl >= 2 && d8) {

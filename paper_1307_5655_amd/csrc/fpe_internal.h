@@ -118,6 +118,15 @@ constexpr int kOpTail = 3;
 constexpr uint32_t kRunCode = 0x800;
 constexpr int kRunMaxGap = 4;
 constexpr int kRunMinOps = 8;
+// The double-float walk's runs (OpF32 run records: the stream offset and the
+// step count as the bits of ah and al): each step top = top * X0 + b as two
+// 64-bit words of runc, the floats (b.h, b.l) and (b's bound term, 0).  Its
+// runs take no gaps (the k - 1 inserted steps of a gap k would have b = 0 and
+// no bound term): measured on MI355X, the extra compensated steps cost more
+// than the dispatch they save, while gap-free runs do exactly the steps of
+// the walk without runs, so the bits do not change.
+constexpr int kRunWordsF32 = 2;
+constexpr int kRunMaxGapF32 = 1;
 
 // Power chain (fast exponentiation, Section 2.2): table[dst] = x_var (LOAD)
 // or table[s1] * table[s2] (MUL), in order.  Entries 0..n_used-1 are the ones
@@ -138,7 +147,8 @@ struct ChainStep {
 struct DevTree {
   const OpF64* ops64;
   const OpF64* ops64r;         // the FP64 chain walk's program: ops64 with runs (see kRunCode)
-  const uint64_t* runc;        // FP64 bits of the runs' coefficients
+  const OpF32* ops32r;         // the double-float chain walk's program: ops32 with runs
+  const uint64_t* runc;        // the runs' coefficients (FP64 bits; double-float: see kRunWordsF32)
   const uint64_t* tc;          // per node: its coefficient (FP64 bits or residue; 0 for junctions)
   const int32_t* te;           // per node: its monomial's exponents (nvars each)
   const OpF32* ops32;
@@ -201,6 +211,7 @@ struct fpe_tree {
   std::vector<fpe::OpF64> ops64;
   std::vector<fpe::OpF32> ops32;
   std::vector<fpe::OpF64> ops64r;       // derived by layout(): ops64 with runs (FP64, depth <= 2), else empty
+  std::vector<fpe::OpF32> ops32r;       // derived by layout(): ops32 with runs (F32C, depth <= 2), else empty
   std::vector<uint64_t> runc;           // the runs' coefficients
   std::vector<uint64_t> term_c;         // FP64 / mod 2^61-1 trees: each node's coefficient (few-point path)
   std::vector<fpe::ChainStep> chain;
@@ -219,7 +230,8 @@ struct fpe_tree {
   double abs_scale = 0;
   // device image
   void* dev = nullptr;
-  size_t off_ops64 = 0, off_ops32 = 0, off_chain = 0, off_coef = 0, off_ops64r = 0, off_runc = 0, dev_bytes = 0;
+  size_t off_ops64 = 0, off_ops32 = 0, off_chain = 0, off_coef = 0, off_ops64r = 0, off_ops32r = 0, off_runc = 0,
+         dev_bytes = 0;
   size_t off_term_c = 0, off_term_e = 0;
 };
 

@@ -305,9 +305,10 @@ bool try_launch(fpe_server* s, Slot& sl) {
       WorkItem& it = table_items(sl.host[c])[n];
       std::memset(&it, 0, sizeof it);
       it.tree = dev_view(q.r.tree);
-      // FP64 requests walk the same program as fpe_evaluate (runs for
-      // chain-like trees); the compensated walk and its fallback the ops
+      // requests walk the same programs as fpe_evaluate (runs for
+      // chain-like trees); the double-double fallback the plain ops
       if (q.r.domain == FPE_F64) it.tree.ops64 = it.tree.ops64r;
+      if (q.r.domain == FPE_F32C) it.tree.ops32 = it.tree.ops32r;
       for (int j = 0; j < q.r.tree->nvars; ++j) it.pts[j] = (const double*)q.r.pts[j];
       it.out = (double*)q.r.out;
       it.cond = q.r.cond_out;

@@ -779,11 +779,55 @@ struct Walker {
   // head, right after issuing the load.
   static __device__ __forceinline__ void settle() { __builtin_amdgcn_s_waitcnt(0xC07F); }
 
-  // A run record (kRunCode): o.b steps top = top * X0 + c, the coefficients
-  // read eight at a time with scalar loads, the next eight in flight while
-  // the current ones are applied.
-  static constexpr bool kRuns = std::is_same_v<Ar, ArF64> && DMAX <= 2;
+  // A run record (kRunCode): steps top = top * X0 + c, the coefficients read
+  // with scalar loads (FP64: eight at a time; double-float: four steps of
+  // two words), the next group in flight while the current one is applied.
+  static constexpr bool kRuns = (std::is_same_v<Ar, ArF64> || std::is_same_v<Ar, ArDF32>) && DMAX <= 2;
   __device__ __forceinline__ void run_chain(const Op& o) {
+    if constexpr (std::is_same_v<Ar, ArF64>) run_chain_f64(o);
+    else run_chain_df32(o);
+  }
+  // double-float: o.ah, o.al carry the stream offset and the step count
+  // (as bits); each step is the NODE_OPEN step with b = (b.h, b.l) and its
+  // bound term from the stream (b = 0 and no bound term in a gap)
+  __device__ __forceinline__ void run_chain_df32(const Op& o) {
+    using CW = const __attribute__((address_space(4))) uint64_t;
+    CW* __restrict__ c = (CW*)runc + (int64_t)kRunWordsF32 * __float_as_uint(o.ah);
+    const int64_t K = (int64_t)__float_as_uint(o.al);
+    Pow X[PPL];
+    FPE_FOR_J { X[j] = rp[j].r[0]; }
+    auto step = [&](uint64_t w0, uint64_t w1) {
+      const float bh = __uint_as_float((uint32_t)w0), bl = __uint_as_float((uint32_t)(w0 >> 32));
+      const float k2 = __uint_as_float((uint32_t)w1);
+      FPE_FOR_J {
+        const Acc t = m[0][j];
+        m[0][j] = df_step<true, false>(t.h, t.l, t.e, t.t, X[j], bh, bl, k2, __builtin_fabsf(bh));
+      }
+    };
+    int64_t i = 0;
+    if (K >= 4) {
+      uint64_t cur[8], nxt[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) cur[k] = c[k];
+      settle();
+#pragma unroll 1
+      for (; i + 8 <= K; i += 4) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) nxt[k] = c[2 * (i + 4) + k];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) step(cur[2 * q], cur[2 * q + 1]);
+        settle();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) step(cur[2 * q], cur[2 * q + 1]);
+      i += 4;
+    }
+#pragma unroll 1
+    for (; i < K; ++i) step(c[2 * i], c[2 * i + 1]);
+  }
+  __device__ __forceinline__ void run_chain_f64(const Op& o) {
     using CW = const __attribute__((address_space(4))) uint64_t;
     CW* __restrict__ c = (CW*)runc + o.a;
     const int64_t K = (int64_t)o.b;
