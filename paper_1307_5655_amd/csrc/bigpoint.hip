@@ -34,6 +34,7 @@ namespace {
 constexpr int kBigPrimes = 2;
 constexpr int kSchoolMax = 64;   // a product whose shorter operand is shorter goes to the schoolbook kernel
 constexpr int kCarryThreads = 1024;
+constexpr int kCarryTable = 15360;   // digit sums t_k a carry workgroup keeps in LDS (60 KB)
 
 // Where a limb array lives: the workspace, the caller's point, or the
 // caller's output (the job lists hold offsets, so they depend only on the
@@ -184,13 +185,26 @@ __global__ __launch_bounds__(kCarryThreads) void k_sum_carry(const Parent* __res
                                                              uint32_t* __restrict__ ws, int32_t* overflow) {
   const Parent Pa = parents[blockIdx.x];
   const int L = Pa.len;
+  // t_k for k = 0..L, computed once with consecutive threads on consecutive
+  // positions (coalesced reads of the children's columns) and kept in LDS;
+  // values too long for it recompute t_k from the columns where needed
+  __shared__ uint32_t ts[kCarryTable];
+  const bool tab = L + 1 <= kCarryTable;
+  if (tab) {
+    for (int k = threadIdx.x; k <= L; k += kCarryThreads) ts[k] = tsum(Pa, jobs, ws, k);
+    __syncthreads();
+  }
+  auto u_at = [&](int k) -> uint32_t {
+    if (tab) return (ts[k] & 0xFFFFu) + (k > 0 ? ts[k - 1] >> 16 : 0u);
+    return usum(Pa, jobs, ws, k);
+  };
   const int per = (L + kCarryThreads - 1) / kCarryThreads;
   const int k0 = threadIdx.x * per, k1 = min(L, k0 + per);
   // this chunk's carry function: generate G (carry out with no carry in) and
   // propagate P (carry out = carry in)
   bool G = false, Pp = true;
   for (int k = k0; k < k1; ++k) {
-    const uint32_t u = usum(Pa, jobs, ws, k);
+    const uint32_t u = u_at(k);
     G = (u > 0xFFFFu) || (u == 0xFFFFu && G);
     Pp = Pp && u == 0xFFFFu;
   }
@@ -215,13 +229,13 @@ __global__ __launch_bounds__(kCarryThreads) void k_sum_carry(const Parent* __res
   uint32_t c = threadIdx.x > 0 ? g_s[threadIdx.x - 1] : 0u;   // carry into this chunk
   uint32_t* out = at(B, Pa.out);
   for (int k = k0; k < k1; ++k) {
-    const uint32_t u = usum(Pa, jobs, ws, k) + c;
+    const uint32_t u = u_at(k) + c;
     out[k] = u & 0xFFFFu;
     c = u >> 16;
   }
   // nothing may be left above the value's length (the host's bound)
-  if (threadIdx.x == kCarryThreads - 1 && (g_s[kCarryThreads - 1] || tsum(Pa, jobs, ws, L) != 0 ||
-                                           usum(Pa, jobs, ws, L) != 0))
+  if (threadIdx.x == kCarryThreads - 1 &&
+      (g_s[kCarryThreads - 1] || (tab ? ts[L] : tsum(Pa, jobs, ws, L)) != 0 || u_at(L) != 0))
     *overflow = 1;
 }
 
