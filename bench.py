@@ -729,6 +729,11 @@ def main():
                     help="run only the rate probes (for a profiler run of the probe kernels) and print them")
     ap.add_argument("--compose-only", action="store_true",
                     help="run only the 4096 x (255 o 15) composition (for a profiler run of its kernels) and print it")
+    ap.add_argument("--interval-only", action="store_true",
+                    help="run only the interval walk over 1e7 boxes (for a profiler run of its kernel) and print it")
+    ap.add_argument("--bigint-only", action="store_true",
+                    help="run only the big-integer phases, many points and one big point (for a profiler run of "
+                         "their kernels) and print them")
     ap.add_argument("--few-points-only", action="store_true",
                     help="run only the few-point trivariate comparison (for a profiler run of the term-parallel "
                          "and walk kernels) and print it")
@@ -759,6 +764,15 @@ def main():
         return
     if args.few_points_only:
         print(json.dumps({"few_points_trivariate": few_points_phase(fpe, fpe_inputs, torch, dev)}), flush=True)
+        return
+    if args.interval_only:
+        print(json.dumps({"interval_1e7": interval_phase(fpe, fpe_inputs, torch, dev, HipEvents(), args.points)}),
+              flush=True)
+        return
+    if args.bigint_only:
+        warm_events(torch)
+        print(json.dumps({"bigint_256bit_points": bigint_phase(fpe, torch, dev),
+                          "bigint_one_512bit_point": bigpoint_phase(fpe, torch, dev)}), flush=True)
         return
     degrees = (3000, 5000)
     schemes = ("balanced", "estrin", "horner")
