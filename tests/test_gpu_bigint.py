@@ -75,6 +75,21 @@ def test_bigint_carry_chains(dev, scheme):
     check(got, exps, cs, xs)
 
 
+def test_bigint_many_points(dev):
+    """600 points (a workgroup each) against the oracle, and the first 40
+    alone give the same limbs."""
+    say("bigint 600 points")
+    g = np.random.default_rng([13075655, 7, 3])
+    n = 30
+    exps = list(range(n + 1))
+    cs = [int(c) | 1 for c in g.integers(0, 2 ** 63, n + 1, dtype=np.uint64)]
+    xs = [int.from_bytes(g.bytes(12), "little") for _ in range(600)]
+    got, t = run(exps, cs, "balanced", xs, 6, dev)
+    check(got[::37], exps, cs, xs[::37])
+    few, _ = run(exps, cs, "balanced", xs[:40], 6, dev)
+    assert np.array_equal(few, got[:40])
+
+
 def test_bigint_errors(dev):
     say("bigint errors")
     t = fpe.Tree(np.array([[0], [5]], dtype=np.int32), np.array([3, 4], dtype=np.uint64), "horner",
