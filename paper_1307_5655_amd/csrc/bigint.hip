@@ -8,8 +8,9 @@
 // words, so a product of two limbs fits in 32 bits and a column of up to
 // 2^16 products fits in 64.  A multiply-add out (+)= a b + c0 is a
 // convolution over the workgroup (thread t sums the columns t, t + 256, ...)
-// into 64-bit columns, then the first wavefront carries the columns into
-// limbs by a carry-lookahead.  Coefficients are uint64 (four limbs); with
+// into 64-bit columns, then a carry-lookahead turns the columns into limbs
+// (one wavefront for short results, ranges of columns over the four
+// wavefronts for long ones).  Coefficients are uint64 (four limbs); with
 // coefficients and points >= 0 every partial value is at most p(x), so every
 // value fits the output's limb count.
 #include <hip/hip_runtime.h>
@@ -52,7 +53,7 @@ struct BigArgs {
 
 // Each operand of up to kBigStage limbs is staged in LDS for the product,
 // and results of up to kBigCols limbs keep their columns in LDS for the carry
-// pass (one wavefront per workgroup: its reads would otherwise wait on L2).
+// pass (its reads would otherwise wait on L2).
 constexpr int kBigStage = 3072;
 constexpr int kBigCols = 4096;
 
@@ -65,45 +66,103 @@ constexpr int kBigCols = 4096;
 // E = 0xFFFF.  With G and P those lanes' ballots, (G | P) + G + c_in is a
 // binary sum whose carry into bit l is exactly column l's carry in.  Columns
 // nhi .. nhi + 2 take the top digits of the last three: anything left there
-// is an overflow (the value needs more than lout limbs).  Writes the nhi
-// limbs of out and returns the result's length (highest nonzero limb + 1,
-// at least 1) in every lane.  Col reads a column from LDS or global memory
-// by its own kind of load (a generic pointer would take flat loads, whose
-// aperture is chosen from the base address, which may lie below the column
-// array when the compiler folds an offset into the load).
+// is an overflow (the value needs more than lout limbs).  Col reads a column
+// from LDS or global memory by its own kind of load (a generic pointer would
+// take flat loads, whose aperture is chosen from the base address, which may
+// lie below the column array when the compiler folds an offset into the load).
 template <class Col>
-__device__ __forceinline__ int carry_pass(int nhi, uint32_t* out, int32_t* overflow, Col col_at) {
-  const int lane = threadIdx.x;
-  uint32_t cin = 0, hprev = 0;
-  int lenv = 1;
-  bool ovf = false;
-  const int ncol = nhi + 3;
-  for (int base = 0; base < ncol; base += kLanes) {
-    const int k = base + lane;
-    uint32_t D = 0;
+__device__ __forceinline__ uint32_t digit_sum(int k, int nhi, Col col_at) {
+  uint32_t D = 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int kk = k - i;
-      if (kk >= 0 && kk < nhi) D += (uint32_t)((col_at(kk) >> (16 * i)) & 0xFFFFu);
-    }
-    const uint32_t lo = D & 0xFFFFu, hi = D >> 16;
+  for (int i = 0; i < 4; ++i) {
+    const int kk = k - i;
+    if (kk >= 0 && kk < nhi) D += (uint32_t)((col_at(kk) >> (16 * i)) & 0xFFFFu);
+  }
+  return D;
+}
+
+// One wavefront carries the columns [b0, b1) (b0 a multiple of 64), entering
+// with carry cin into column b0 and hprev = D(b0 - 1) / 2^16; on return cin
+// and hprev are those of the column after the last chunk.  kWrite: write the
+// limbs below nhi, raise ovf for a nonzero limb above and keep lenv (highest
+// nonzero limb + 1); otherwise only clear allp if some column of the range
+// does not propagate (the range's carry out is then independent of cin).
+template <bool kWrite, class Col>
+__device__ __forceinline__ void carry_range(int nhi, int b0, int b1, uint32_t& cin, uint32_t& hprev, uint32_t* out,
+                                            int& lenv, bool& ovf, bool& allp, Col col_at) {
+  const int lane = threadIdx.x & (kLanes - 1);
+  for (int base = b0; base < b1; base += kLanes) {
+    const int k = base + lane;
+    const uint32_t D = digit_sum(k, nhi, col_at);
+    const uint32_t hi = D >> 16;
     uint32_t hb = (uint32_t)__shfl_up((int)hi, 1);
     if (lane == 0) hb = hprev;
-    const uint32_t E = lo + hb;
+    const uint32_t E = (D & 0xFFFFu) + hb;
     const uint64_t G = __ballot(E > 0xFFFFu), Pm = __ballot(E == 0xFFFFu);
     const uint64_t Am = G | Pm;
     const uint64_t cm = (Am + G + cin) ^ Am ^ G;   // bit l: carry into column base + l
-    const uint32_t limb = (E + (uint32_t)((cm >> lane) & 1u)) & 0xFFFFu;
-    if (k < nhi) out[k] = limb;
-    else if (limb) ovf = true;
-    const uint64_t nz = __ballot(k < nhi && limb != 0);
-    if (nz) lenv = base + 64 - __clzll((long long)nz);
+    if (kWrite) {
+      const uint32_t limb = (E + (uint32_t)((cm >> lane) & 1u)) & 0xFFFFu;
+      if (k < nhi) out[k] = limb;
+      else if (limb) ovf = true;
+      const uint64_t nz = __ballot(k < nhi && limb != 0);
+      if (nz) lenv = base + 64 - __clzll((long long)nz);
+    } else if (Pm != ~0ull) {
+      allp = false;
+    }
     cin = (uint32_t)(((G >> 63) | ((Pm >> 63) & (cm >> 63))) & 1u);
     hprev = (uint32_t)__shfl((int)hi, kLanes - 1);
   }
-  if (cin || hprev) ovf = true;
+}
+
+// Carries columns 0 .. nhi + 2 into the nhi limbs of out and returns the
+// result's length (at least 1) in every thread; every thread of the workgroup
+// calls it.  Short results are one wavefront's.  Longer ones are split into
+// kW contiguous ranges, one per wavefront: a first pass gives each range's
+// carry out with no carry in and whether every column of it propagates; a
+// range's carry in is then the carry out of the ranges below, composed in
+// order (g_w | (p_w & c)), and a second pass writes the limbs.
+template <int kW, class Col>
+__device__ __forceinline__ int carry_columns(int nhi, uint32_t* out, int32_t* overflow, Col col_at) {
+  __shared__ uint32_t rg[kW], rp[kW];
+  __shared__ int rlen[kW];
+  const int lane = threadIdx.x & (kLanes - 1), w = threadIdx.x / kLanes;
+  const int ncol = nhi + 3, nch = (ncol + kLanes - 1) / kLanes;
+  int lenv = 1;
+  bool ovf = false, allp = true;
+  if (kW == 1 || nch < 2 * kW) {
+    if (w == 0) {
+      uint32_t cin = 0, hprev = 0;
+      carry_range<true>(nhi, 0, ncol, cin, hprev, out, lenv, ovf, allp, col_at);
+      if (cin || hprev) ovf = true;
+      if (ovf) *overflow = 1;
+      if (lane == 0) rlen[0] = lenv;
+    }
+    __syncthreads();
+    return rlen[0];
+  }
+  const int q = (nch + kW - 1) / kW * kLanes;   // columns per wavefront
+  const int b0 = w * q, b1 = min(b0 + q, ncol);
+  const uint32_t h0 = b0 > 0 && b0 < ncol ? digit_sum(b0 - 1, nhi, col_at) >> 16 : 0u;
+  uint32_t cin = 0, hprev = h0;
+  carry_range<false>(nhi, b0, b1, cin, hprev, out, lenv, ovf, allp, col_at);
+  if (lane == 0) {
+    rg[w] = cin;
+    rp[w] = allp ? 1u : 0u;
+  }
+  __syncthreads();
+  cin = 0;
+  for (int i = 0; i < w; ++i) cin = rg[i] | (rp[i] & cin);
+  hprev = h0;
+  carry_range<true>(nhi, b0, b1, cin, hprev, out, lenv, ovf, allp, col_at);
+  if (b0 < ncol && b1 == ncol && (cin || hprev)) ovf = true;   // the top range
   if (ovf) *overflow = 1;
-  return lenv;
+  if (lane == 0) rlen[w] = lenv;
+  __syncthreads();
+  int n = rlen[0];
+#pragma unroll
+  for (int i = 1; i < kW; ++i) n = max(n, rlen[i]);
+  return n;
 }
 
 // out (+)= a[0 .. la) * b[0 .. lb) + c0, where out holds lacc limbs when
@@ -117,7 +176,6 @@ __device__ int big_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uin
   constexpr int kThreads = kW * kLanes;
   __shared__ uint32_t sa[kBigStage], sb[kBigStage];
   __shared__ uint64_t scol[kBigCols];
-  __shared__ int len_s;
   const int lane = threadIdx.x;
   const int lp = min(la + lb - 1, lout);
   // limbs the result can reach: the product, the accumulated value and the
@@ -130,8 +188,8 @@ __device__ int big_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uin
     for (int k = lane; k < lb; k += kThreads) sb[k] = b[k];
   __syncthreads();
   const bool lds_cols = nhi <= kBigCols;
-  // the column sums; both operands staged (the common case) read LDS by LDS
-  // loads, otherwise each from where it lives
+  // the column sums; each operand is read from where it lives by that
+  // memory's own loads (no generic pointer that may point at LDS)
   auto columns = [&](auto rd_a, auto rd_b) {
     for (int k = lane; k < nhi; k += kThreads) {
       uint64_t s = 0;
@@ -145,27 +203,24 @@ __device__ int big_mac(const uint32_t* a, int la, const uint32_t* b, int lb, uin
       else col[k] = s;
     }
   };
-  if (stage_a && stage_b) {
-    columns([&](int i) { return sa[i]; }, [&](int i) { return sb[i]; });
+  auto lds_a = [&](int i) { return sa[i]; };
+  auto lds_b = [&](int i) { return sb[i]; };
+  auto mem_a = [&](int i) { return a[i]; };
+  auto mem_b = [&](int i) { return b[i]; };
+  if (stage_a) {
+    if (stage_b) columns(lds_a, lds_b);
+    else columns(lds_a, mem_b);
   } else {
-    const uint32_t* A = stage_a ? sa : a;
-    const uint32_t* Bv = stage_b ? sb : b;
-    columns([&](int i) { return A[i]; }, [&](int i) { return Bv[i]; });
+    if (stage_b) columns(mem_a, lds_b);
+    else columns(mem_a, mem_b);
   }
   __syncthreads();
-  // the carry is one wavefront's (the first)
-  if (lane < kLanes) {
-    int n;
-    if (lds_cols) n = carry_pass(nhi, out, overflow, [&](int kk) { return scol[kk]; });
-    else n = carry_pass(nhi, out, overflow, [&](int kk) { return col[kk]; });
-    if (lane == 0) len_s = n;
-  }
-  __syncthreads();
-  return len_s;
+  if (lds_cols) return carry_columns<kW>(nhi, out, overflow, [&](int kk) { return scol[kk]; });
+  return carry_columns<kW>(nhi, out, overflow, [&](int kk) { return col[kk]; });
 }
 
-// kW wavefronts per point: their lanes share a product's columns (the
-// carry stays with the first).
+// kW wavefronts per point: their lanes share a product's columns and, for
+// long results, its carry.
 template <int kW>
 __global__ __launch_bounds__(kW * kLanes) void k_bigint_walk(BigArgs A) {
   constexpr int kThreads = kW * kLanes;

@@ -75,6 +75,21 @@ def test_bigint_carry_chains(dev, scheme):
     check(got, exps, cs, xs)
 
 
+@pytest.mark.parametrize("scheme", ["horner", "balanced"])
+def test_bigint_carry_across_ranges(dev, scheme):
+    """Points 2^(16 m) - 1 (m limbs of 0xFFFF) make p(x) = x^2 + x + c0 carry
+    from its low limbs through whole runs of propagating columns: results of
+    450 to 10,000 limbs, whose carry is split into ranges over the
+    workgroup's wavefronts (every column of a middle range propagates), with
+    operands too long for LDS and columns in global memory at the top."""
+    say(f"bigint carry across wavefront ranges, {scheme}")
+    lx = 5000
+    xs = [2 ** (16 * m) - 1 for m in (223, 446, 1000, 2047, 5000)] + [2 ** (16 * 5000) - 2, 2 ** (16 * 4999), 0, 1]
+    for cs in ([1, 1, 1], [2 ** 64 - 1, 1, 1], [1, 2 ** 64 - 1, 1]):
+        got, t = run([0, 1, 2], cs, scheme, xs, lx, dev)
+        check(got, [0, 1, 2], cs, xs)
+
+
 def test_bigint_many_points(dev):
     """600 points (a workgroup each) against the oracle, and the first 40
     alone give the same limbs."""
