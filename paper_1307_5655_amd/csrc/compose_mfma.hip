@@ -323,9 +323,12 @@ __global__ __launch_bounds__(256, 3) void k_cm_mfma(GLists Ls, CBases B) {
       int64_t v = 0;
 #pragma unroll
       for (int g = 0; g < kGroups; ++g) v += (int64_t)acc[g][rr] * (int64_t(1) << kShift[g]);
-      // |v| < 2^31 (2^24 + 2^17 + 2^16 + 2^9 + 2^8 + 3) < 2^56: add 2^27 p
-      atomicAdd((unsigned long long*)&obuf[tile * kObufTile + row * 33 + u],
-                (unsigned long long)reduce31((uint64_t)(v + ((int64_t)kP31 << 27))));
+      // |v| < 2^31 (2^24 + 2^17 + 2^16 + 2^9 + 2^8 + 3) < 2^56, added as a
+      // two's-complement 64-bit word: each wavefront's share of the tiles is
+      // contiguous in tile order, so it flushes a tile at most once and a
+      // tile's sum has at most kWaves terms, |sum| < 2^58 (reduced once, in
+      // the output pass)
+      atomicAdd((unsigned long long*)&obuf[tile * kObufTile + row * 33 + u], (unsigned long long)v);
     }
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) acc[g] = i32x16{};
@@ -387,7 +390,8 @@ __global__ __launch_bounds__(256, 3) void k_cm_mfma(GLists Ls, CBases B) {
     const GParent& P = Pl[o.parent];
     const int n = 32 * (m - o.base) + row;
     if (n >= P.lout) continue;
-    uint64_t v = obuf[tile * kObufTile + row * 33 + col];
+    // the signed sum plus 2^28 p (> 2^58) is non-negative and below 2^60
+    uint64_t v = (uint64_t)((int64_t)obuf[tile * kObufTile + row * 33 + col] + ((int64_t)kP31 << 28));
     if (n == 0) v += Cl[o.parent];
     optr(B, P.out, inst)[n] = reduce31(v);
   }
