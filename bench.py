@@ -531,6 +531,39 @@ def bigpoint_phase(fpe, torch, dev, reps: int = 3):
     return res
 
 
+def compose_bigint_phase(fpe, torch, dev, reps: int = 3):
+    """Composition over the natural numbers at one big point (fpe_compose_bigint:
+    Kronecker substitution into the walk at one big point): p with 64-bit
+    coefficients and 16..18 or 32..34 terms, q of degree 3 with 64-bit
+    coefficients; time per scheme (single calls) and the ratio to balanced."""
+    g = np.random.default_rng([13075655, 10])
+    q = [int(c) for c in g.integers(1, 2 ** 63, 4, dtype=np.uint64)]
+    res = {}
+    for n in (15, 16, 17, 31, 32, 33):
+        ex = np.arange(n + 1, dtype=np.int32).reshape(-1, 1)
+        co = g.integers(1, 2 ** 63, n + 1, dtype=np.uint64)
+        row = {}
+        for s in ("balanced", "estrin", "horner"):
+            t = fpe.Tree(ex, co, s, fpe.BIGINT).upload(dev)
+            out = fpe.compose_bigint(t, q)
+            ws = torch.empty(fpe.compose_bigint_workspace_bytes(t, q) + 256, dtype=torch.uint8, device=dev)
+            fpe.compose_bigint(t, q, out=out, workspace=ws)
+            ms = []
+            for _ in range(reps):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fpe.compose_bigint(t, q, out=out, workspace=ws, check=False)
+                e1.record()
+                torch.cuda.synchronize()
+                ms.append(e0.elapsed_time(e1))
+            row[s] = float(np.median(ms))
+        res[f"terms{n + 1}"] = {"ms": row, "estrin_over_balanced": row["estrin"] / row["balanced"],
+                                "horner_over_balanced": row["horner"] / row["balanced"],
+                                "coef_limbs": int(out.shape[1]), "coefs": int(out.shape[0])}
+    return res
+
+
 def warm_events(torch):
     """Record and wait on one pair of torch timing events: their first use
     sets up state on the host (tens of milliseconds), which would otherwise
@@ -779,7 +812,8 @@ def main():
     if args.bigint_only:
         warm_events(torch)
         print(json.dumps({"bigint_256bit_points": bigint_phase(fpe, torch, dev),
-                          "bigint_one_512bit_point": bigpoint_phase(fpe, torch, dev)}), flush=True)
+                          "bigint_one_512bit_point": bigpoint_phase(fpe, torch, dev),
+                          "compose_bigint_one_point": compose_bigint_phase(fpe, torch, dev)}), flush=True)
         return
     degrees = (3000, 5000)
     schemes = ("balanced", "estrin", "horner")
@@ -938,7 +972,7 @@ def main():
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
 
-    probes = dense = served = latency = modp = compose = ival = big = modp_roof = compose_methods = bigpoint = None
+    probes = dense = served = latency = modp = compose = ival = big = modp_roof = compose_methods = bigpoint = compose_big = None
     few = None
     if not args.no_extra:
         log("rate probes")
@@ -962,6 +996,8 @@ def main():
         big = bigint_phase(fpe, torch, dev)
         log("one big point")
         bigpoint = bigpoint_phase(fpe, torch, dev)
+        log("composition over the integers at one big point")
+        compose_big = compose_bigint_phase(fpe, torch, dev)
 
     cpu = None
     if not args.no_cpu:
@@ -1007,6 +1043,7 @@ def main():
         "interval_1e7": ival,
         "bigint_256bit_points": big,
         "bigint_one_512bit_point": bigpoint,
+        "compose_bigint_one_point": compose_big,
     }
     # no child process is ever started; the device buffers of the phases are
     # released before the line is printed, so the process ends right after it

@@ -337,8 +337,38 @@ int64_t fpe_bigpoint_out_limbs(const fpe_tree* t, int32_t lx);
 size_t fpe_bigpoint_workspace_bytes(const fpe_tree* t, int32_t lx);
 fpe_status fpe_eval_bigpoint(const fpe_tree* t, const uint32_t* x, int32_t lx, uint32_t* out, int64_t lout,
                              void* workspace, size_t workspace_bytes, void* stream);
-/* Waits for stream, then reads the overflow flag that the last fpe_eval_bigint
- * or fpe_eval_bigpoint on this workspace wrote (a value needed more than lout limbs, which the
+/* Composition over the natural numbers at one big point: the coefficients of
+ * p(q(X)), the title problem with integer elements, whose size grows with the
+ * degree (Section 1.2).  p is the tree (univariate, FPE_BIGINT, uint64
+ * coefficients >= 0), q has uint64 coefficients >= 0.  By Kronecker
+ * substitution: every coefficient of p(q(X)) is at most p(q(1)), so with
+ * slots of lc 16-bit limbs, 2^(16 lc) > p(q(1)), the natural number
+ * p(q(2^(16 lc))) holds the coefficient of X^k in its limbs
+ * [k lc, (k + 1) lc); q(2^(16 lc)) is q's coefficients one per slot, and p at
+ * that point is fpe_eval_bigpoint's level walk (Figure 1's setting: one big
+ * point, the tree's scheme deciding the products).
+ *   q    HOST uint64[dq + 1], q[0] + q[1] X + ..., 0 <= dq < 64; read during
+ *        the call
+ *   out  device uint32[lout]: coefficient k (k = 0 .. deg p * dq) as lc
+ *        16-bit limbs (values < 2^16, least significant first) at
+ *        out[k lc .. (k + 1) lc), zero beyond; lout >=
+ *        fpe_compose_bigint_out_limbs(t, q, dq) = (deg p * dq + 1) lc
+ *   workspace  device buffer of fpe_compose_bigint_workspace_bytes(t, q, dq)
+ *        bytes, 256-byte aligned; its first 4 bytes are the overflow flag
+ *        that fpe_bigint_status reads
+ * fpe_compose_bigint_coef_limbs returns lc, or 0 when unsupported: dq >= 64,
+ * or a product of the walk longer than 2^14 limbs (the point and p(point)
+ * must fit the big-point walk).
+ * Errors: FPE_EINVAL (not a FPE_BIGINT tree, lout too small, NULL, dq < 0),
+ * FPE_ENOMEM (workspace), FPE_EUNSUPPORTED. */
+int32_t fpe_compose_bigint_coef_limbs(const fpe_tree* t, const uint64_t* q, int32_t dq);
+int64_t fpe_compose_bigint_out_limbs(const fpe_tree* t, const uint64_t* q, int32_t dq);
+size_t fpe_compose_bigint_workspace_bytes(const fpe_tree* t, const uint64_t* q, int32_t dq);
+fpe_status fpe_compose_bigint(const fpe_tree* t, const uint64_t* q, int32_t dq, uint32_t* out, int64_t lout,
+                              void* workspace, size_t workspace_bytes, void* stream);
+/* Waits for stream, then reads the overflow flag that the last fpe_eval_bigint,
+ * fpe_eval_bigpoint or fpe_compose_bigint on this workspace wrote (a value
+ * needed more than lout limbs, which the
  * host's lout bound rules out; a device-side check).  FPE_OK, or FPE_ENOMEM
  * if the result was truncated.  This call synchronises; fpe_eval_bigint does not. */
 fpe_status fpe_bigint_status(const void* workspace, void* stream);

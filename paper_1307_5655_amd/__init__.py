@@ -133,6 +133,10 @@ def _load():
         "fpe_bigpoint_out_limbs": ([P, i32], i64),
         "fpe_bigpoint_workspace_bytes": ([P, i32], sz),
         "fpe_eval_bigpoint": ([P, P, i32, P, i64, P, sz, P], i32),
+        "fpe_compose_bigint_coef_limbs": ([P, P, i32], i32),
+        "fpe_compose_bigint_out_limbs": ([P, P, i32], i64),
+        "fpe_compose_bigint_workspace_bytes": ([P, P, i32], sz),
+        "fpe_compose_bigint": ([P, P, i32, P, i64, P, sz, P], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)
@@ -429,6 +433,51 @@ def eval_bigpoint(tree: Tree, x, out=None, workspace=None, stream=None, check=Tr
     if check:
         _check(lib.fpe_bigint_status(ctypes.c_void_p(workspace.data_ptr() + off), _stream_ptr(stream)))
     return out
+
+
+def _q_u64(q):
+    import numpy as np
+    return np.ascontiguousarray(np.asarray([int(c) for c in q], dtype=np.uint64))
+
+
+def compose_bigint_workspace_bytes(tree: Tree, q) -> int:
+    qa = _q_u64(q)
+    return int(lib.fpe_compose_bigint_workspace_bytes(tree.handle, ctypes.c_void_p(qa.ctypes.data), len(qa) - 1))
+
+
+def compose_bigint(tree: Tree, q, out=None, workspace=None, stream=None, check=True):
+    """p(q(X)) over the natural numbers (fpe_compose_bigint): ``tree`` is an
+    uploaded FPE_BIGINT tree, ``q`` the inner polynomial's coefficients
+    (sequence of ints in [0, 2^64), q[0] first, at most 64).  Returns a device
+    int32 tensor [deg p * dq + 1, lc]: row k holds the coefficient of X^k as
+    16-bit limbs, least significant first.  With ``check`` the overflow flag
+    is read back (fpe_bigint_status, which waits for the stream)."""
+    import torch
+    if tree._dev is None:
+        raise FpeError(-1, "tree is not uploaded")
+    qa = _q_u64(q)
+    dq = len(qa) - 1
+    qp = ctypes.c_void_p(qa.ctypes.data)
+    lc = int(lib.fpe_compose_bigint_coef_limbs(tree.handle, qp, dq))
+    if lc <= 0:
+        raise FpeError(-5, "composition at one big point: unsupported size")
+    nout = int(lib.fpe_compose_bigint_out_limbs(tree.handle, qp, dq))
+    dev = tree._dev.device
+    if out is None:
+        out = torch.empty(nout, dtype=torch.int32, device=dev)
+    elif out.numel() < nout or not out.is_contiguous() or out.element_size() != 4:
+        raise FpeError(-1, f"out must be a contiguous 32-bit tensor of at least {nout} limbs")
+    out = out.view(-1)
+    need = int(lib.fpe_compose_bigint_workspace_bytes(tree.handle, qp, dq))
+    if workspace is None:
+        workspace = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    off = (-workspace.data_ptr()) % 256
+    _check(lib.fpe_compose_bigint(tree.handle, qp, dq, ctypes.c_void_p(out.data_ptr()), out.numel(),
+                                  ctypes.c_void_p(workspace.data_ptr() + off), workspace.numel() - off,
+                                  _stream_ptr(stream)))
+    if check:
+        _check(lib.fpe_bigint_status(ctypes.c_void_p(workspace.data_ptr() + off), _stream_ptr(stream)))
+    return out[:nout].view(nout // lc, lc)
 
 
 def compose_workspace_bytes(tree: Tree, dq: int, product=PRODUCT_AUTO) -> int:

@@ -12,7 +12,7 @@ LIB = os.path.join(HERE, "libfpe.so")
 PROBE_LIB = os.path.join(HERE, "libfpe_probe.so")
 PROBE_SOURCES = ["probes.hip"]
 SOURCES = ["compile.cpp", "api.cpp", "walk.hip", "eval_f64.hip", "eval_terms.hip", "eval_m61.hip", "eval_df32.hip", "eval_iv.hip", "bigint.hip",
-           "serve_kernels.hip", "compose.hip", "ntt.hip", "compose_mfma.hip", "bigpoint.hip",
+           "serve_kernels.hip", "compose.hip", "ntt.hip", "compose_mfma.hip", "bigpoint.hip", "compose_bigint.hip",
            "server.cpp"]
 EXTRA_SOURCES = []
 

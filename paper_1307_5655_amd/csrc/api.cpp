@@ -535,6 +535,27 @@ fpe_status fpe_eval_bigpoint(const fpe_tree* t, const uint32_t* x, int32_t lx, u
   return launch_bigpoint(t, x, lx, out, lout, workspace, workspace_bytes, stream);
 }
 
+int32_t fpe_compose_bigint_coef_limbs(const fpe_tree* t, const uint64_t* q, int32_t dq) {
+  return compose_bigint_plan(t, q, dq).lc;
+}
+
+int64_t fpe_compose_bigint_out_limbs(const fpe_tree* t, const uint64_t* q, int32_t dq) {
+  return compose_bigint_plan(t, q, dq).nout;
+}
+
+size_t fpe_compose_bigint_workspace_bytes(const fpe_tree* t, const uint64_t* q, int32_t dq) {
+  return compose_bigint_plan(t, q, dq).bytes;
+}
+
+fpe_status fpe_compose_bigint(const fpe_tree* t, const uint64_t* q, int32_t dq, uint32_t* out, int64_t lout,
+                              void* workspace, size_t workspace_bytes, void* stream) {
+  if (!t || !q || !out) return fail(FPE_EINVAL, "NULL argument");
+  if (!t->dev) return fail(FPE_EINVAL, "tree is not uploaded");
+  if (t->domain != FPE_BIGINT) return fail(FPE_EINVAL, "the tree is not compiled for FPE_BIGINT");
+  if (dq < 0) return fail(FPE_EINVAL, "dq < 0");
+  return launch_compose_bigint(t, q, dq, out, lout, workspace, workspace_bytes, stream);
+}
+
 fpe_status fpe_bigint_status(const void* workspace, void* stream) {
   if (!workspace) return fail(FPE_EINVAL, "NULL workspace");
   int32_t flag = 0;

@@ -289,6 +289,20 @@ size_t bigpoint_workspace_bytes(const fpe_tree* t, int32_t lx);
 fpe_status launch_bigpoint(const fpe_tree* t, const uint32_t* x, int32_t lx, uint32_t* out, int64_t lout, void* ws,
                            size_t ws_bytes, void* stream);
 void bigpoint_forget(const fpe_tree* t);
+// composition over the natural numbers at one big point, by Kronecker
+// substitution into the big-point walk (compose_bigint.hip)
+constexpr int kComposeBigMaxQ = 64;          // coefficients of q, passed as kernel arguments
+constexpr int64_t kBigPointMaxLimbs = 1 << 14;   // the largest transform of the big-point walk
+struct ComposeBigPlan {
+  int32_t lc = 0;       // limbs per coefficient slot (0: unsupported)
+  int64_t ly = 0;       // limbs of the point y = q(2^(16 lc))
+  int64_t lz = 0;       // limbs of p(y) as the big-point walk writes it
+  int64_t nout = 0;     // (deg p * dq + 1) * lc
+  size_t off_y = 0, off_z = 0, bytes = 0;   // workspace: walk's, y, p(y)
+};
+ComposeBigPlan compose_bigint_plan(const fpe_tree* t, const uint64_t* q, int32_t dq);
+fpe_status launch_compose_bigint(const fpe_tree* t, const uint64_t* q, int32_t dq, uint32_t* out, int64_t lout,
+                                 void* ws, size_t ws_bytes, void* stream);
 constexpr int kMaxDepth = 15;   // stack depth the kernels hold (the code's 4-bit level field)
 constexpr int kBigMaxLimbs = 1 << 16;   // big-integer values: columns of 2^16 limb products fit in 64 bits
 constexpr int kMaxTable = 48;   // power-table entries held per point (composition)

@@ -1,5 +1,7 @@
 """GPU big-integer evaluation (FPE_BIGINT) through the C-ABI, bit-exact
 against the oracle's exact integers (p(x) = sum c_m x^m in Python ints)."""
+import math
+
 import numpy as np
 import pytest
 import torch
@@ -171,3 +173,72 @@ def test_bigpoint_special_points_and_errors(dev):
     with pytest.raises(fpe.FpeError) as e:
         fpe.eval_bigpoint(t, torch.ones(1024, dtype=torch.int32, device=dev))
     assert "2^14" in str(e.value)
+
+
+def compose_case(dev, p, q, scheme):
+    """fpe_compose_bigint of p (dense coefficient list, zeros dropped) with q
+    against the oracle's composition over the integers, every limb."""
+    exps = [e for e, c in enumerate(p) if c]
+    cs = [int(p[e]) for e in exps]
+    t = fpe.Tree(np.asarray(exps, dtype=np.int32).reshape(-1, 1), np.asarray(cs, dtype=np.uint64), scheme,
+                 fpe.BIGINT).upload(dev)
+    got = fpe.compose_bigint(t, q)
+    torch.cuda.synchronize()
+    g = got.cpu().numpy()
+    want = bigint.compose_int([((e,), c) for e, c in zip(exps, cs)], q)
+    assert g.shape[0] == len(want)
+    assert np.all((g >= 0) & (g < 1 << 16))
+    for k, w in enumerate(want):
+        assert bigint.from_limbs(g[k].astype(np.int64)) == w, k
+    return g
+
+
+@pytest.mark.parametrize("scheme", ["horner", "estrin", "balanced"])
+def test_compose_bigint_exact(dev, scheme):
+    """p(q(X)) over the natural numbers (Kronecker substitution into the walk
+    at one big point): 64-bit coefficients with zeros in both polynomials,
+    every coefficient of the result exact."""
+    say(f"compose bigint, {scheme}")
+    g = np.random.default_rng([13075655, 9, 1])
+    p = [int(c) for c in g.integers(0, 2 ** 63, 21, dtype=np.uint64) * 2 + 1]
+    p[4] = p[11] = 0
+    p[7] = 2 ** 64 - 1
+    q = [2 ** 64 - 1, 0, int(g.integers(1, 2 ** 63)), 12345]
+    compose_case(dev, p, q, scheme)
+    # term counts at and past a power of two, q of degree 3
+    for n in (16, 17, 33):
+        p = [int(c) | 1 for c in g.integers(0, 2 ** 63, n, dtype=np.uint64)]
+        compose_case(dev, p, [int(c) for c in g.integers(0, 2 ** 63, 4, dtype=np.uint64)], scheme)
+
+
+def test_compose_bigint_special_cases(dev):
+    """Closed forms and degenerate inputs: X^n o (X + 1) gives the binomial
+    coefficients; q = X gives p back; a constant q gives the constant p(q);
+    a constant p gives itself; a single-term p; q with a zero constant."""
+    say("compose bigint special cases")
+    for n in (1, 12, 40):
+        p = [0] * n + [1]
+        r = compose_case(dev, p, [1, 1], "balanced")
+        assert [bigint.from_limbs(r[k].astype(np.int64)) for k in range(n + 1)] == [math.comb(n, k) for k in range(n + 1)]
+    p = [3, 0, 2 ** 64 - 1, 7, 1]
+    compose_case(dev, p, [0, 1], "estrin")
+    compose_case(dev, p, [2 ** 40 + 3], "horner")
+    compose_case(dev, [5], [1, 2, 3], "horner")
+    compose_case(dev, [0, 0, 0, 9], [0, 2 ** 63, 1], "balanced")
+
+
+def test_compose_bigint_limits(dev):
+    """q of 65 coefficients and results beyond the big-point walk's 2^14-limb
+    products are refused; the largest bench size runs."""
+    say("compose bigint limits")
+    t = fpe.Tree(np.arange(3, dtype=np.int32).reshape(-1, 1), np.array([1, 2, 3], dtype=np.uint64), "horner",
+                 fpe.BIGINT).upload(dev)
+    with pytest.raises(fpe.FpeError):
+        fpe.compose_bigint(t, [1] * 65)
+    big = fpe.Tree(np.arange(200, dtype=np.int32).reshape(-1, 1), np.full(200, 2 ** 63, dtype=np.uint64),
+                   "balanced", fpe.BIGINT).upload(dev)
+    with pytest.raises(fpe.FpeError):
+        fpe.compose_bigint(big, [2 ** 63] * 8)
+    g = np.random.default_rng([13075655, 9, 2])
+    p = [int(c) | 1 for c in g.integers(0, 2 ** 63, 34, dtype=np.uint64)]
+    compose_case(dev, p, [int(c) for c in g.integers(0, 2 ** 63, 4, dtype=np.uint64)], "balanced")
