@@ -23,13 +23,13 @@ void build_runs(fpe_tree* t) {
   t->ops64r.clear();
   t->ops32r.clear();
   t->runc.clear();
+  t->runc64.clear();
   const bool f32 = t->domain == FPE_F32C;
   if ((t->domain != FPE_F64 && !f32) || t->depth > 2 || t->n_offtable > 0 || t->n_table < 1 ||
       t->table_deg[0] <= 0 || (f32 && t->ops32.size() != t->ops64.size()))
     return;
   const int32_t v0 = t->table_var[0], d0 = t->table_deg[0];
-  const int max_gap = f32 ? kRunMaxGapF32 : kRunMaxGap;
-  auto unit_steps = [&](const OpF64& o) -> int {   // steps of x^d0 the op is; 0: not a chain step
+  auto unit_steps = [&](const OpF64& o, int max_gap) -> int {   // steps of x^d0 the op is; 0: not a chain step
     if (op_kind(o.info) != kNodeOpen || op_level(o.info) != 1 || op_pidx2(o.info) != kNoPair) return 0;
     const uint32_t p = op_pidx(o.info);
     if (p == kOffTable || (int32_t)p >= t->n_table || t->table_var[p] != v0 || t->table_deg[p] % d0) return 0;
@@ -48,51 +48,72 @@ void build_runs(fpe_tree* t) {
     return f;
   };
   const size_t n = t->ops64.size();
-  std::vector<OpF64> prog;
-  std::vector<OpF32> prog32;
-  std::vector<uint64_t> coefs;
-  bool any = false;
-  for (size_t i = 0; i < n;) {
-    size_t j = i;
-    while (j < n && unit_steps(t->ops64[j]) > 0) ++j;
-    if (j - i >= (size_t)kRunMinOps) {
-      if (f32) {
-        OpF32 r = t->ops32[i];
-        const size_t first = coefs.size() / kRunWordsF32;
-        for (size_t k = i; k < j; ++k) {
-          for (int z = 1; z < unit_steps(t->ops64[k]); ++z) {   // b = 0, no bound term
-            coefs.push_back(0);
-            coefs.push_back(0);
-          }
-          coefs.push_back(word2(t->ops32[k].bh, t->ops32[k].bl));
-          coefs.push_back(word2(t->ops32[k].bk2, 0.f));
-        }
-        r.ah = bits32((uint32_t)first);
-        r.al = bits32((uint32_t)(coefs.size() / kRunWordsF32 - first));
-        r.deg = kRunCode << 20;
-        prog32.push_back(r);
-      } else {
+  // the FP64 program with runs (FP64 trees' walk; a compensated tree's
+  // double-double fallback, which reads the FP64 records): gaps of up to
+  // kRunMaxGap steps of x^d0
+  {
+    std::vector<OpF64> prog;
+    std::vector<uint64_t> coefs;
+    bool any = false;
+    for (size_t i = 0; i < n;) {
+      size_t j = i;
+      while (j < n && unit_steps(t->ops64[j], kRunMaxGap) > 0) ++j;
+      if (j - i >= (size_t)kRunMinOps) {
         OpF64 r = t->ops64[i];
         r.a = coefs.size();
         for (size_t k = i; k < j; ++k) {
-          for (int z = 1; z < unit_steps(t->ops64[k]); ++z) coefs.push_back(0);   // +0.0
+          for (int z = 1; z < unit_steps(t->ops64[k], kRunMaxGap); ++z) coefs.push_back(0);   // +0.0
           coefs.push_back(t->ops64[k].b);
         }
         r.b = coefs.size() - r.a;
         r.deg = kRunCode << 20;
         prog.push_back(r);
+        any = true;
+        i = j;
+      } else {
+        prog.push_back(t->ops64[i]);
+        ++i;
       }
+    }
+    if (any && coefs.size() <= 0x7fffffffu) {
+      t->ops64r = std::move(prog);
+      if (f32) t->runc64 = std::move(coefs);
+      else t->runc = std::move(coefs);
+    }
+  }
+  if (!f32) return;
+  // the double-float program with runs: gap-free (a compensated step costs
+  // more than the dispatch a gap step would save)
+  std::vector<OpF32> prog32;
+  std::vector<uint64_t> coefs;
+  bool any = false;
+  for (size_t i = 0; i < n;) {
+    size_t j = i;
+    while (j < n && unit_steps(t->ops64[j], kRunMaxGapF32) > 0) ++j;
+    if (j - i >= (size_t)kRunMinOps) {
+      OpF32 r = t->ops32[i];
+      const size_t first = coefs.size() / kRunWordsF32;
+      for (size_t k = i; k < j; ++k) {
+        for (int z = 1; z < unit_steps(t->ops64[k], kRunMaxGapF32); ++z) {   // b = 0, no bound term
+          coefs.push_back(0);
+          coefs.push_back(0);
+        }
+        coefs.push_back(word2(t->ops32[k].bh, t->ops32[k].bl));
+        coefs.push_back(word2(t->ops32[k].bk2, 0.f));
+      }
+      r.ah = bits32((uint32_t)first);
+      r.al = bits32((uint32_t)(coefs.size() / kRunWordsF32 - first));
+      r.deg = kRunCode << 20;
+      prog32.push_back(r);
       any = true;
       i = j;
     } else {
-      if (f32) prog32.push_back(t->ops32[i]);
-      else prog.push_back(t->ops64[i]);
+      prog32.push_back(t->ops32[i]);
       ++i;
     }
   }
   if (!any || coefs.size() / 2 > 0x7fffffffu) return;
-  if (f32) t->ops32r = std::move(prog32);
-  else t->ops64r = std::move(prog);
+  t->ops32r = std::move(prog32);
   t->runc = std::move(coefs);
 }
 
@@ -132,6 +153,8 @@ void layout(fpe_tree* t) {
   if (!t->ops32r.empty()) off = align256(off + (t->ops32r.size() + kOpTail) * sizeof(OpF32));
   t->off_runc = off;
   if (!t->runc.empty()) off = align256(off + t->runc.size() * sizeof(uint64_t));
+  t->off_runc64 = off;
+  if (!t->runc64.empty()) off = align256(off + t->runc64.size() * sizeof(uint64_t));
   t->off_term_c = off;
   if (!t->term_c.empty()) off = align256(off + t->term_c.size() * sizeof(uint64_t));
   t->off_term_e = off;
@@ -147,6 +170,7 @@ DevTree dev_view(const fpe_tree* t) {
   d.ops64r = t->ops64r.empty() ? d.ops64 : (const OpF64*)(b + t->off_ops64r);
   d.ops32r = t->ops32r.empty() ? (const OpF32*)(b + t->off_ops32) : (const OpF32*)(b + t->off_ops32r);
   d.runc = (const uint64_t*)(b + t->off_runc);
+  d.runc64 = (const uint64_t*)(b + t->off_runc64);
   d.tc = (const uint64_t*)(b + t->off_term_c);
   d.te = (const int32_t*)(b + t->off_term_e);
   d.ops32 = (const OpF32*)(b + t->off_ops32);
@@ -278,6 +302,9 @@ fpe_status fpe_tree_upload(fpe_tree* t, void* dev_buf, size_t bytes, void* strea
   }
   if (e == hipSuccess && !t->runc.empty())
     e = hipMemcpyAsync(b + t->off_runc, t->runc.data(), t->runc.size() * sizeof(uint64_t), hipMemcpyHostToDevice, st);
+  if (e == hipSuccess && !t->runc64.empty())
+    e = hipMemcpyAsync(b + t->off_runc64, t->runc64.data(), t->runc64.size() * sizeof(uint64_t),
+                       hipMemcpyHostToDevice, st);
   if (e == hipSuccess && !t->term_c.empty()) {
     e = hipMemcpyAsync(b + t->off_term_c, t->term_c.data(), t->term_c.size() * sizeof(uint64_t),
                        hipMemcpyHostToDevice, st);

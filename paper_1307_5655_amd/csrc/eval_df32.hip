@@ -114,10 +114,14 @@ static void gofb(const KernelLaunch& L, const int32_t* list, const int64_t* coun
 
 void launch_fallback(const KernelLaunch& L, const int32_t* list, const int64_t* count, double* out) {
   const bool d2 = L.tr.depth <= 2, d6 = L.tr.depth <= 6, d8 = L.tr.depth <= 8;
+  // the chain-like kernels read the FP64 program with runs
+  KernelLaunch R = L;
+  R.tr.ops64 = L.tr.ops64r;
   if (L.offt) {
     if (d8) gofb<8, 1, true>(L, list, count, out); else gofb<kMaxDepth, 1, true>(L, list, count, out);
-  } else if (L.ppl >= 2 && d2) {
-    gofb<2, 2, false>(L, list, count, out);
+  } else if (d2) {
+    if (L.ppl >= 2) gofb<2, 2, false>(R, list, count, out);
+    else gofb<2, 1, false>(R, list, count, out);
   } else if (L.ppl >= 2 && d6) {
     gofb<6, 2, false>(L, list, count, out);
   } else if (L.ppl >= 2 && d8) {

@@ -149,6 +149,7 @@ struct DevTree {
   const OpF64* ops64r;         // the FP64 chain walk's program: ops64 with runs (see kRunCode)
   const OpF32* ops32r;         // the double-float chain walk's program: ops32 with runs
   const uint64_t* runc;        // the runs' coefficients (FP64 bits; double-float: see kRunWordsF32)
+  const uint64_t* runc64;      // a compensated tree's FP64 run coefficients (its double-double fallback)
   const uint64_t* tc;          // per node: its coefficient (FP64 bits or residue; 0 for junctions)
   const int32_t* te;           // per node: its monomial's exponents (nvars each)
   const OpF32* ops32;
@@ -213,6 +214,7 @@ struct fpe_tree {
   std::vector<fpe::OpF64> ops64r;       // derived by layout(): ops64 with runs (FP64, depth <= 2), else empty
   std::vector<fpe::OpF32> ops32r;       // derived by layout(): ops32 with runs (F32C, depth <= 2), else empty
   std::vector<uint64_t> runc;           // the runs' coefficients
+  std::vector<uint64_t> runc64;         // F32C trees: the FP64 runs' coefficients (ops64r, double-double fallback)
   std::vector<uint64_t> term_c;         // FP64 / mod 2^61-1 trees: each node's coefficient (few-point path)
   std::vector<fpe::ChainStep> chain;
   std::vector<int32_t> table_var, table_deg;   // per table entry
@@ -231,7 +233,7 @@ struct fpe_tree {
   // device image
   void* dev = nullptr;
   size_t off_ops64 = 0, off_ops32 = 0, off_chain = 0, off_coef = 0, off_ops64r = 0, off_ops32r = 0, off_runc = 0,
-         dev_bytes = 0;
+         off_runc64 = 0, dev_bytes = 0;
   size_t off_term_c = 0, off_term_e = 0;
 };
 

@@ -306,9 +306,13 @@ bool try_launch(fpe_server* s, Slot& sl) {
       std::memset(&it, 0, sizeof it);
       it.tree = dev_view(q.r.tree);
       // requests walk the same programs as fpe_evaluate (runs for
-      // chain-like trees); the double-double fallback the plain ops
+      // chain-like trees), the double-double fallback of a compensated
+      // request its FP64 program with runs
       if (q.r.domain == FPE_F64) it.tree.ops64 = it.tree.ops64r;
-      if (q.r.domain == FPE_F32C) it.tree.ops32 = it.tree.ops32r;
+      if (q.r.domain == FPE_F32C) {
+        it.tree.ops32 = it.tree.ops32r;
+        it.tree.ops64 = it.tree.ops64r;
+      }
       for (int j = 0; j < q.r.tree->nvars; ++j) it.pts[j] = (const double*)q.r.pts[j];
       it.out = (double*)q.r.out;
       it.cond = q.r.cond_out;

@@ -782,9 +782,11 @@ struct Walker {
   // A run record (kRunCode): steps top = top * X0 + c, the coefficients read
   // with scalar loads (FP64: eight at a time; double-float: four steps of
   // two words), the next group in flight while the current one is applied.
-  static constexpr bool kRuns = (std::is_same_v<Ar, ArF64> || std::is_same_v<Ar, ArDF32>) && DMAX <= 2;
+  static constexpr bool kRuns =
+      (std::is_same_v<Ar, ArF64> || std::is_same_v<Ar, ArDF32> || std::is_same_v<Ar, ArDD>) && DMAX <= 2;
   __device__ __forceinline__ void run_chain(const Op& o) {
     if constexpr (std::is_same_v<Ar, ArF64>) run_chain_f64(o);
+    else if constexpr (std::is_same_v<Ar, ArDD>) run_chain_dd(o);
     else run_chain_df32(o);
   }
   // double-float: o.ah, o.al carry the stream offset and the step count
@@ -862,6 +864,46 @@ struct Walker {
     for (; i < K; ++i) {
       const double ck = u2d(c[i]);
       FPE_FOR_J { m[0][j] = __builtin_fma(m[0][j], X[j], ck); }
+    }
+  }
+
+  // double-double (the compensated walk's fallback): the FP64 runs, each
+  // step exactly the walk's NODE_OPEN step top = top X0 + c
+  __device__ __forceinline__ void run_chain_dd(const Op& o) {
+    using CW = const __attribute__((address_space(4))) uint64_t;
+    CW* __restrict__ c = (CW*)runc + o.a;
+    const int64_t K = (int64_t)o.b;
+    Pow X[PPL];
+    FPE_FOR_J { X[j] = rp[j].r[0]; }
+    auto apply = [&](const uint64_t (&cc)[8]) {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const DD ck{u2d(cc[k]), 0.0};
+        FPE_FOR_J { m[0][j] = dd_fma<true, false>(m[0][j], X[j], ck); }
+      }
+    };
+    int64_t i = 0;
+    if (K >= 8) {
+      uint64_t cur[8], nxt[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) cur[k] = c[k];
+      settle();
+#pragma unroll 1
+      for (; i + 16 <= K; i += 8) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) nxt[k] = c[i + 8 + k];
+        apply(cur);
+        settle();
+#pragma unroll
+        for (int k = 0; k < 8; ++k) cur[k] = nxt[k];
+      }
+      apply(cur);
+      i += 8;
+    }
+#pragma unroll 1
+    for (; i < K; ++i) {
+      const DD ck{u2d(c[i]), 0.0};
+      FPE_FOR_J { m[0][j] = dd_fma<true, false>(m[0][j], X[j], ck); }
     }
   }
 
@@ -969,7 +1011,7 @@ struct Walker {
 
   __device__ __forceinline__ void run(const DevTree& tr) {
     ops = Ar::ops(tr);
-    runc = tr.runc;
+    runc = std::is_same_v<Ar, ArDD> ? tr.runc64 : tr.runc;
 #pragma unroll
     for (int j = 0; j < PPL; ++j) {
       tab[j].build(tr, x[j], rp[j]);
