@@ -90,6 +90,13 @@ def test_bigint_carry_across_ranges(dev, scheme):
     for cs in ([1, 1, 1], [2 ** 64 - 1, 1, 1], [1, 2 ** 64 - 1, 1]):
         got, t = run([0, 1, 2], cs, scheme, xs, lx, dev)
         check(got, [0, 1, 2], cs, xs)
+    # more points than compute units (the other workgroup width), rows checked
+    # against the oracle and against the small batch
+    many = xs * 34
+    got_many, _ = run([0, 1, 2], [2 ** 64 - 1, 1, 1], scheme, many, lx, dev)
+    check(got_many[::17], [0, 1, 2], [2 ** 64 - 1, 1, 1], many[::17])
+    few, _ = run([0, 1, 2], [2 ** 64 - 1, 1, 1], scheme, xs, lx, dev)
+    assert np.array_equal(got_many[:len(xs)], few)
 
 
 def test_bigint_many_points(dev):
