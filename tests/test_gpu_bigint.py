@@ -232,6 +232,9 @@ def test_compose_bigint_special_cases(dev):
     compose_case(dev, p, [2 ** 40 + 3], "horner")
     compose_case(dev, [5], [1, 2, 3], "horner")
     compose_case(dev, [0, 0, 0, 9], [0, 2 ** 63, 1], "balanced")
+    # the zero polynomial inside: only p(0) is left
+    compose_case(dev, [7, 3, 0, 2 ** 64 - 1], [0], "estrin")
+    compose_case(dev, [7, 3, 0, 2 ** 64 - 1], [0, 0, 0], "balanced")
 
 
 def test_compose_bigint_limits(dev):
@@ -249,3 +252,5 @@ def test_compose_bigint_limits(dev):
     g = np.random.default_rng([13075655, 9, 2])
     p = [int(c) | 1 for c in g.integers(0, 2 ** 63, 34, dtype=np.uint64)]
     compose_case(dev, p, [int(c) for c in g.integers(0, 2 ** 63, 4, dtype=np.uint64)], "balanced")
+    # every coefficient at its largest: the slot bound is met with the least slack
+    compose_case(dev, [2 ** 64 - 1] * 30, [2 ** 64 - 1] * 4, "estrin")
