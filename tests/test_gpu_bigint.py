@@ -1,5 +1,7 @@
 """GPU big-integer evaluation (FPE_BIGINT) through the C-ABI, bit-exact
-against the oracle's exact integers (p(x) = sum c_m x^m in Python ints)."""
+against the oracle's exact integers (p(x) = sum c_m x^m in Python ints), and
+composition over the natural numbers at one big point against the oracle's
+composition by its definition (sum c_m q^m)."""
 import math
 
 import numpy as np
